@@ -1,0 +1,372 @@
+"""Pins that tie the CPU oracle to the paper and to mathematics, not to itself.
+
+Each pin takes an oracle instance and returns ``(error, bound)``; the pin holds
+when ``error <= bound``.  They are collected in ``PINS`` so that the planted-
+mistake test can run the whole battery against deliberately broken copies of
+the oracle and check that every planted mistake trips at least one pin.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+from refmath import pos, size, regular_closed, singular_closed, max_degree_error
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _unit(rng):
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def _cluster(rng, n=20, half=0.5, centre=(0, 0, 0)):
+    pts = rng.uniform(-half, half, (n, 3)) + np.asarray(centre, float)
+    q = rng.uniform(-1, 1, n)
+    return pts, q
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _random_solid(rng, P, decay=0.5):
+    C = np.zeros(size(P))
+    for n in range(P):
+        for m in range(n + 1):
+            s = decay ** n / math.factorial(n + m) ** 0.5
+            C[pos(n, m)] = rng.normal() * s
+            C[pos(n, m) + 1] = rng.normal() * s if m else 0.0
+    return C
+
+
+# ---------------------------------------------------------------- harmonics
+def pin_regular_closed_form(o):
+    """R by the Appendix recurrence == spherical closed form (Legendre, no CS phase)."""
+    rng = _rng(11)
+    err = 0.0
+    for _ in range(4):
+        r = rng.normal(size=3) * 1.3
+        err = max(err, max_degree_error(o.regular(r, 12), regular_closed(r, 12), 12, "M"))
+    return err, 1e-13
+
+
+def pin_singular_closed_form(o):
+    """S by the Appendix recurrence == spherical closed form."""
+    rng = _rng(12)
+    err = 0.0
+    for _ in range(4):
+        r = rng.normal(size=3) * 1.3
+        err = max(err, max_degree_error(o.singular(r, 12), singular_closed(r, 12), 12, "L"))
+    return err, 1e-13
+
+
+def pin_zaxis_singular_golden(o):
+    """S_n^m(0,0,R) == n!/R^{n+1} delta_{m0} (Section 2.3), exact-rational fixture."""
+    err = 0.0
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "zaxis_singular.txt")):
+        if line.startswith("#"):
+            continue
+        R, n, m, re, im = line.split()
+        rows.setdefault(R, []).append((int(n), int(m), float(Fraction(re)), float(Fraction(im))))
+    for R, entries in rows.items():
+        P = 1 + max(e[0] for e in entries)
+        S = o.singular([0.0, 0.0, float(Fraction(R))], P)
+        for n, m, re, im in entries:
+            scale = max(abs(re), 1e-300) if m == 0 else float(Fraction(math.factorial(n))) / float(Fraction(R)) ** (n + 1)
+            err = max(err, abs(S[pos(n, m)] - re) / scale, abs(S[pos(n, m) + 1] - im) / scale)
+    return err, 4e-16
+
+
+def pin_regular_diagonal_and_axis(o):
+    """R_n^n = (x+iy)^n / (2^n n!) and R_n^0(0,0,z) = z^n / n! (consequences of the Appendix)."""
+    rng = _rng(13)
+    r = rng.normal(size=3)
+    P = 14
+    R = o.regular(r, P)
+    err = 0.0
+    w = complex(r[0], r[1])
+    for n in range(P):
+        ref = w ** n / (2 ** n * math.factorial(n))
+        got = complex(R[pos(n, n)], R[pos(n, n) + 1] if n else 0.0)
+        err = max(err, abs(got - ref) / abs(ref))
+    z = 1.7
+    Rz = o.regular([0.0, 0.0, z], P)
+    for n in range(P):
+        ref = z ** n / math.factorial(n)
+        err = max(err, abs(Rz[pos(n, 0)] - ref) / ref)
+        for m in range(1, n + 1):
+            err = max(err, abs(Rz[pos(n, m)]) + abs(Rz[pos(n, m) + 1]))
+    return err, 1e-14
+
+
+def pin_addition_theorem(o):
+    """1/|x-y| = sum_n sum_m R_n^m(y) conj(S_n^m(x)) for |y| < |x|, error ~ (|y|/|x|)^P."""
+    rng = _rng(14)
+    worst = 0.0
+    for _ in range(3):
+        x = _unit(rng) * 2.0
+        y = _unit(rng) * 0.5
+        exact = 1.0 / np.linalg.norm(x - y)
+        for P in (8, 16, 24):
+            R = o.regular(y, P)
+            S = o.singular(x, P)
+            acc = 0.0
+            for n in range(P):
+                acc += R[pos(n, 0)] * S[pos(n, 0)]
+                for m in range(1, n + 1):
+                    # m and -m together: 2 Re(R conj(S))
+                    acc += 2 * (R[pos(n, m)] * S[pos(n, m)] + R[pos(n, m) + 1] * S[pos(n, m) + 1])
+            bound = 2.0 * 0.25 ** P / (1 - 0.25) + 1e-15
+            worst = max(worst, abs(acc - exact) / exact / bound)
+    return worst, 1.0
+
+
+# ---------------------------------------------------------------- M2L
+def pin_m2l_charge_at_centre(o):
+    """A unit charge at x_A: M = (q, 0, ...) and L_n^m = q S_n^m(x_A - x_B) exactly, every degree."""
+    rng = _rng(21)
+    err = 0.0
+    for _ in range(3):
+        r = _unit(rng) * rng.uniform(2, 4)
+        P = 10
+        M = o.p2m(P, [0, 0, 0], [[0.0, 0.0, 0.0]], [0.7])
+        L = o.m2l(P, P, r, M)
+        ref = 0.7 * singular_closed(-r, P)
+        err = max(err, max_degree_error(L, ref, P, "L"))
+    return err, 1e-13
+
+
+def _golden_zaxis_m2l():
+    M, L = {}, {}
+    for line in open(os.path.join(GOLDEN, "zaxis_m2l.txt")):
+        if line.startswith("#"):
+            continue
+        t, a, b, re, im = line.split()
+        (M if t == "M" else L)[(int(a), int(b))] = (float(Fraction(re)), float(Fraction(im)))
+    P = 1 + max(k for k, _ in M)
+    Mv = np.zeros(size(P))
+    for (k, m), (re, im) in M.items():
+        Mv[pos(k, m)] = re
+        Mv[pos(k, m) + 1] = im
+    Lv = np.zeros(size(P))
+    for (n, m), (re, im) in L.items():
+        Lv[pos(n, m)] = re
+        Lv[pos(n, m) + 1] = im
+    return P, Mv, Lv
+
+
+def pin_m2l_zaxis_golden(o):
+    """Shift (0,0,1): L_n^m = (-1)^{n+m} sum_{k>=m} M_k^m (n+k)!  (eq. zm2lkernels), exact fixture."""
+    P, M, Lref = _golden_zaxis_m2l()
+    L = o.m2l(P, P, [0.0, 0.0, 1.0], M)
+    return _rel(L, Lref), 1e-15
+
+
+def pin_m2l_zaxis_scaled(o):
+    """Shift (0,0,R): S_{n+k}^{m+l}(0,0,R) = delta (n+k)!/R^{n+k+1}, random M, mixed orders."""
+    rng = _rng(22)
+    err = 0.0
+    for (p_in, p_out, R) in ((6, 6, 2.5), (7, 4, 3.0), (3, 8, 2.2)):
+        M = _random_solid(rng, p_in)
+        for sgn in (1.0, -1.0):
+            L = o.m2l(p_in, p_out, [0.0, 0.0, sgn * R], M)
+            ref = np.zeros(size(p_out))
+            for n in range(p_out):
+                for m in range(n + 1):
+                    for c in (0, 1):
+                        if c == 1 and m == 0:
+                            continue
+                        acc = 0.0
+                        for k in range(m, p_in):
+                            # S at (0,0,-R) picks up (-1)^{n+k}; the (-1)^m of conj(M^{-m}) and
+                            # the (-1)^n prefactor combine to (-1)^{n+m}
+                            s = 1.0 if sgn > 0 else (-1.0) ** (n + k)
+                            acc += s * M[pos(k, m) + c] * math.factorial(n + k) / R ** (n + k + 1)
+                        ref[pos(n, m) + c] = (-1) ** (n + m) * acc
+            err = max(err, max_degree_error(L, ref, p_out, "L"))
+    return err, 1e-14
+
+
+def pin_m2l_vs_direct(o):
+    """P2M -> M2L -> evaluate L == direct sum, error decaying with P (eq. nbody)."""
+    rng = _rng(23)
+    pts, q = _cluster(rng, 20)
+    r = np.array([2.1, -1.3, 1.7])  # |r| ~ 3
+    targets = r + rng.uniform(-0.5, 0.5, (6, 3))
+    exact = np.array([o.direct(pts, q, t) for t in targets])
+    errs = []
+    for P in (4, 8, 12, 16):
+        M = o.p2m(P, [0, 0, 0], pts, q)
+        L = o.m2l(P, P, r, M)
+        got = np.array([o.eval_l(P, r, L, t) for t in targets])
+        errs.append(np.max(np.abs(got - exact)) / np.max(np.abs(exact)))
+    decaying = all(errs[i + 1] < errs[i] * 0.2 for i in range(3))
+    # geometric bound with rho = |y|max + |x-xB|max = 0.87 + 0.87 against |r| ~ 3
+    ok_abs = errs[-1] < 1e-7
+    return (0.0 if (decaying and ok_abs) else 1.0), 0.5
+
+
+def pin_m2l_mixed_orders(o):
+    """The rows of a small p_out are the leading rows of a larger p_out (same p_in)."""
+    rng = _rng(24)
+    pts, q = _cluster(rng, 10)
+    M = o.p2m(9, [0, 0, 0], pts, q)
+    r = _unit(rng) * 3.0
+    big = o.m2l(9, 12, r, M)
+    small = o.m2l(9, 5, r, M)
+    return _rel(small, big[: size(5)]), 0.0
+
+
+# ---------------------------------------------------------------- M2M
+def pin_m2m_exact(o):
+    """M2M of P2M at x_A equals P2M at x_A + r (exact for truncated M2M)."""
+    rng = _rng(31)
+    err = 0.0
+    for P in (6, 12):
+        pts, q = _cluster(rng, 15)
+        M = o.p2m(P, [0, 0, 0], pts, q)
+        r = _unit(rng) * rng.uniform(0.25, 0.5)
+        ref = o.p2m(P, r, pts, q)
+        err = max(err, max_degree_error(o.m2m(P, P, r, M), ref, P, "M"))
+    return err, 1e-13
+
+
+def pin_m2m_composition(o):
+    """M2M(a) then M2M(b) == M2M(a+b), and M2M(0) is the identity."""
+    rng = _rng(32)
+    P = 10
+    pts, q = _cluster(rng, 15)
+    M = o.p2m(P, [0, 0, 0], pts, q)
+    a = _unit(rng) * 0.3
+    b = _unit(rng) * 0.4
+    two = o.m2m(P, P, b, o.m2m(P, P, a, M))
+    one = o.m2m(P, P, a + b, M)
+    e1 = max_degree_error(two, one, P, "M")
+    e0 = _rel(o.m2m(P, P, [0.0, 0.0, 0.0], M), M)
+    return max(e1, e0), 1e-13
+
+
+def pin_m2m_mixed_orders(o):
+    """p_in < p_out: rows n < p_in are exact; rows n >= p_in equal P2M of the truncated input."""
+    rng = _rng(33)
+    pts, q = _cluster(rng, 12)
+    p_in, p_out = 5, 9
+    Mbig = o.p2m(p_out, [0, 0, 0], pts, q)
+    Min = Mbig[: size(p_in)]
+    r = _unit(rng) * 0.4
+    out = o.m2m(p_in, p_out, r, Min)
+    padded = np.zeros(size(p_out))
+    padded[: size(p_in)] = Min
+    ref = o.m2m(p_out, p_out, r, padded)
+    ref_exact = o.p2m(p_out, r, pts, q)
+    e1 = _rel(out, ref)
+    e2 = max_degree_error(out[: size(p_in)], ref_exact[: size(p_in)], p_in, "M")
+    return max(e1, e2), 1e-13
+
+
+# ---------------------------------------------------------------- L2L
+def pin_l2l_polynomial(o):
+    """An L expansion is a polynomial: re-centring preserves its values everywhere."""
+    rng = _rng(41)
+    err = 0.0
+    for P in (5, 10):
+        L = _random_solid(rng, P, decay=0.8)
+        r = _unit(rng) * rng.uniform(0.25, 0.5)
+        L2 = o.l2l(P, P, r, L)
+        for _ in range(4):
+            x = rng.uniform(-0.6, 0.6, 3)
+            a = o.eval_l(P, [0, 0, 0], L, x)
+            b = o.eval_l(P, r, L2, x)
+            err = max(err, abs(a - b) / max(1e-3, abs(a)))
+    return err, 1e-12
+
+
+def pin_l2l_composition(o):
+    """L2L(a) then L2L(b) == L2L(a+b), and L2L(0) is the identity."""
+    rng = _rng(42)
+    P = 9
+    L = _random_solid(rng, P, decay=0.8)
+    a = _unit(rng) * 0.3
+    b = _unit(rng) * 0.45
+    two = o.l2l(P, P, b, o.l2l(P, P, a, L))
+    one = o.l2l(P, P, a + b, L)
+    e1 = _rel(two, one)
+    e0 = _rel(o.l2l(P, P, [0.0, 0.0, 0.0], L), L)
+    return max(e1, e0), 1e-13
+
+
+def pin_l2l_mixed_orders(o):
+    """p_out < p_in keeps the leading rows; p_out > p_in gives zero rows k >= p_in."""
+    rng = _rng(43)
+    L = _random_solid(rng, 8, decay=0.8)
+    r = _unit(rng) * 0.4
+    full = o.l2l(8, 8, r, L)
+    small = o.l2l(8, 5, r, L)
+    big = o.l2l(8, 11, r, L)
+    e = max(_rel(small, full[: size(5)]), _rel(big[: size(8)], full))
+    e = max(e, float(np.max(np.abs(big[size(8):]))))
+    return e, 0.0
+
+
+def pin_l2l_after_m2l_vs_direct(o):
+    """P2M -> M2L -> L2L -> evaluate == direct, to the truncation accuracy of the M2L."""
+    rng = _rng(44)
+    pts, q = _cluster(rng, 20)
+    r = np.array([0.0, 3.2, 0.4])
+    P = 14
+    M = o.p2m(P, [0, 0, 0], pts, q)
+    L = o.m2l(P, P, r, M)
+    s = np.array([0.2, -0.15, 0.25])
+    L2 = o.l2l(P, P, s, L)
+    worst = 0.0
+    for _ in range(4):
+        t = r + s + rng.uniform(-0.2, 0.2, 3)
+        worst = max(worst, abs(o.eval_l(P, r + s, L2, t) - o.direct(pts, q, t)) / abs(o.direct(pts, q, t)))
+    return worst, 1e-8
+
+
+# ---------------------------------------------------------------- evaluation
+def pin_eval_m_far_field(o):
+    """The M expansion reproduces the direct potential outside the cluster, error ~ (a/|x|)^P."""
+    rng = _rng(51)
+    pts, q = _cluster(rng, 20)
+    P = 16
+    M = o.p2m(P, [0, 0, 0], pts, q)
+    worst = 0.0
+    for _ in range(4):
+        x = _unit(rng) * 4.0
+        worst = max(worst, abs(o.eval_m(P, [0, 0, 0], M, x) - o.direct(pts, q, x)) / abs(o.direct(pts, q, x)))
+    return worst, 1e-9
+
+
+PINS = [
+    pin_regular_closed_form,
+    pin_singular_closed_form,
+    pin_zaxis_singular_golden,
+    pin_regular_diagonal_and_axis,
+    pin_addition_theorem,
+    pin_m2l_charge_at_centre,
+    pin_m2l_zaxis_golden,
+    pin_m2l_zaxis_scaled,
+    pin_m2l_vs_direct,
+    pin_m2l_mixed_orders,
+    pin_m2m_exact,
+    pin_m2m_composition,
+    pin_m2m_mixed_orders,
+    pin_l2l_polynomial,
+    pin_l2l_composition,
+    pin_l2l_mixed_orders,
+    pin_l2l_after_m2l_vs_direct,
+    pin_eval_m_far_field,
+]
