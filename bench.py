@@ -1,0 +1,227 @@
+"""Benchmark of the batched translations on one MI355X.
+
+A step is one pass of the whole path over the uniform-octree batch: 2^20 M2L at P=10
+(shifts from the 316 well-separated offsets, multipoles of 32 points per unit box),
+plus 2^17 parent/child M2M and 2^17 L2L (offsets (+-1/4)^3; the L2L inputs are M2L
+outputs), all FP64 in the paper's basis.  Inputs are generated and resident in HBM
+before the timed region.  ``value`` is M2L translations per second of whole steps
+(the M2M and L2L time counts against it).
+
+Also reported (outside the timed steps): M2L at P=16 and P=30 on the same generator,
+the FP32 normalised-basis path, the direct O(P^4) kernel, per-kernel HIP-event times,
+the roofline of the dominant kernel and the CPU oracle timed on this host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "M2L translations/s at P=10/16/30 vs plain FP64 path; p50/p99 job latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def solid(P):
+    return P * (P + 1)
+
+
+def bytes_per_translation(p_in, p_out, elem):
+    """Algorithmic HBM bytes of one translation: input solid + output solid + shift."""
+    return (solid(p_in) + solid(p_out) + 3) * elem
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_octree_inputs(sh, ctx, torch, dev, P, n, npts=32, seed_config=2, n_child=0):
+    from paper_2202_02847_amd import workloads as wl
+
+    c = wl.config2(n_m2l=n, n_child=max(n_child, 1), npts=npts, P=P, seed_config=seed_config)
+    d_pts = torch.from_numpy(c["pts"]).to(dev)
+    d_q = torch.from_numpy(c["q"]).to(dev)
+    d_c = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    d_M = torch.empty((n, solid(P)), dtype=torch.float64, device=dev)
+    sh.sh_p2m_batch_f64(ctx, P, n, d_c, npts, d_pts, d_q, d_M, solid(P))
+    d_r = torch.from_numpy(c["r_m2l"]).to(dev)
+    out = {"M": d_M, "r": d_r, "r_m2m": torch.from_numpy(c["r_m2m"]).to(dev),
+           "r_l2l": torch.from_numpy(c["r_l2l"]).to(dev)}
+    del d_pts, d_q, d_c
+    torch.cuda.synchronize()
+    return out
+
+
+def time_launch(torch, fn, reps):
+    """Average duration of fn() over reps launches, HIP events on torch's current stream
+    (the stream the library launches on by default)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(seconds_target=10.0):
+    import oracle
+    from paper_2202_02847_amd import workloads as wl
+
+    o = oracle.get()
+    threads = len(os.sched_getaffinity(0))
+    P = 10
+    # calibrate on a small sample, then time a sample sized to ~seconds_target
+    c = wl.config2(n_m2l=1 << 12, n_child=8, P=P)
+    M = o.p2m_batch(P, np.zeros((1 << 12, 3)), c["pts"], c["q"], nthreads=threads)
+    r = c["r_m2l"]
+    t0 = time.perf_counter()
+    o.translate_batch("m2l", P, P, r[:512], M[:512], nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = int(min(1 << 20, max(1024, 512 * seconds_target / max(dt, 1e-6))))
+    reps = (n + len(M) - 1) // len(M)
+    Mr = np.tile(M, (reps, 1))[:n]
+    rr = np.tile(r, (reps, 1))[:n]
+    t0 = time.perf_counter()
+    o.translate_batch("m2l", P, P, rr, Mr, nthreads=threads)
+    dt = time.perf_counter() - t0
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / dt, "unit": "translations/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} M2L at P=10 FP64 (octree shifts, 32-point multipoles), "
+                      f"double-height O(P^4) sum, OpenMP over {threads} threads, {dt:.1f} s; {cpu}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip P=16/30, FP32 and naive extras")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2202_02847_amd as sh
+
+    dev = torch.device("cuda:0")
+    ctx = sh.Context(max_order=32, device=0)
+    P, n, nc = 10, 1 << 20, 1 << 17
+    log(f"[bench] generating octree inputs P={P} n={n}")
+    I = make_octree_inputs(sh, ctx, torch, dev, P, n, n_child=nc)
+    S = solid(P)
+    d_M, d_r = I["M"], I["r"]
+    d_L = torch.empty((n, S), dtype=torch.float64, device=dev)
+    d_M2 = torch.empty((nc, S), dtype=torch.float64, device=dev)
+    d_L2 = torch.empty((nc, S), dtype=torch.float64, device=dev)
+    r_m2m, r_l2l = I["r_m2m"][:nc].contiguous(), I["r_l2l"][:nc].contiguous()
+
+    ev = []
+
+    def m2l():
+        sh.sh_m2l_batch_f64(ctx, P, P, n, d_r, d_M, S, d_L, S)
+
+    def step(record=False):
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        m2l()
+        if record:
+            e1.record()
+            ev.append((e0, e1))
+        sh.sh_m2m_batch_f64(ctx, P, P, nc, r_m2m, d_M, S, d_M2, S)
+        sh.sh_l2l_batch_f64(ctx, P, P, nc, r_l2l, d_L, S, d_L2, S)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(record=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert ctx.device_error() == 0
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    m2l_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    value = n / (ms_step / 1e3)
+    bpt = bytes_per_translation(P, P, 8)
+    achieved = bpt * n / m2l_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "M2L P=10 FP64", "bytes_per_translation": bpt, "launch_ms": round(m2l_s * 1e3, 4)}
+    extra = {"m2l_p10_f64_per_s": n / m2l_s,
+             "m2m_l2l_per_step_ms": round(ms_step - m2l_s * 1e3, 4),
+             "all_translations_per_s": (n + 2 * nc) / (ms_step / 1e3)}
+
+    if not args.no_extra:
+        # FP32 (normalised basis) at P=10 on the same multipoles
+        w = torch.ones(S, dtype=torch.float64, device=dev)
+        import math
+        for nn in range(P):
+            for m in range(nn + 1):
+                v = math.sqrt(math.factorial(nn + m) * math.factorial(nn - m))
+                w[nn * (nn + 1) + 2 * m] = v
+                w[nn * (nn + 1) + 2 * m + 1] = v
+        d_M32 = (d_M * w).float()
+        d_r32 = d_r.float()
+        d_L32 = torch.empty((n, S), dtype=torch.float32, device=dev)
+        t = time_launch(torch, lambda: sh.sh_m2l_batch_f32(ctx, P, P, n, d_r32, d_M32, S, d_L32, S), 5)
+        extra["m2l_p10_f32_per_s"] = n / t
+        extra["m2l_p10_f32_frac_hbm"] = bytes_per_translation(P, P, 4) * n / t / 1e9 / HBM_PEAK_GBS
+        del d_M32, d_L32
+        nv = 1 << 16
+        t = time_launch(torch, lambda: sh.sh_m2l_naive_batch_f64(ctx, P, P, nv, d_r, d_M, S, d_L, S), 3)
+        extra["m2l_p10_naive_f64_per_s"] = nv / t
+        del d_M, d_L, d_M2, d_L2, I
+        torch.cuda.empty_cache()
+        for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
+            log(f"[bench] extra P={PP} n={nn_}")
+            J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)
+            SS = solid(PP)
+            d_out = torch.empty((nn_, SS), dtype=torch.float64, device=dev)
+            t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, PP, PP, nn_, J["r"], J["M"], SS, d_out, SS), 3)
+            extra[f"m2l_p{PP}_f64_per_s"] = nn_ / t
+            extra[f"m2l_p{PP}_f64_frac_hbm"] = bytes_per_translation(PP, PP, 8) * nn_ / t / 1e9 / HBM_PEAK_GBS
+            del J, d_out
+            torch.cuda.empty_cache()
+
+    line = {"metric": METRIC, "value": value, "unit": "translations/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "uniform-octree batch: 2^20 M2L at P=10 (316 well-separated offsets, "
+                                   "32-point multipoles) + 2^17 M2M + 2^17 L2L (offsets (+-1/4)^3), FP64",
+                       "P": P, "m2l_per_step": n, "m2m_per_step": nc, "l2l_per_step": nc},
+            "roofline": roofline}
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

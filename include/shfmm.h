@@ -1,0 +1,187 @@
+/*
+ * shfmm -- solid-harmonic FMM translations (M2M, M2L, L2L) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  The operations are those of Kirchhart, "solidfmm: A highly
+ * optimised library of operations on the solid harmonics for use in fast multipole
+ * methods" (arXiv 2202.02847):
+ *   - M2L (Section 2.1, eq. m2lkernels, double-height kernel), computed by the
+ *     rotation-based scheme of Section 3.4 (scale, z-rotate, swap x<->z, z-rotate, swap,
+ *     z-translate along (0,0,1), and back);
+ *   - M2M and L2L (named in Section 1.2, "very similar", formulas omitted there): the
+ *     same scheme with the z-axis shift of the regular harmonics, R_j^0(0,0,t) = t^j/j!.
+ * The library keeps the paper's interface properties (Section 1.1): single and double
+ * precision, input order != output order, arbitrary shift vectors, a small handle-based
+ * interface, thread safety (a context is immutable after creation) and no exception
+ * crossing the interface (status codes only).
+ *
+ * SOLID LAYOUT (Section 2.1, Fig. 1).  An expansion ("solid") of order P holds degrees
+ * n = 0..P-1 and orders m = 0..n as P(P+1) reals: Re C_n^m at index n(n+1)+2m and
+ * Im C_n^m at n(n+1)+2m+1.  Negative orders are implied by C_n^{-m} = (-1)^m conj(C_n^m).
+ * Im C_n^0 is ignored on input and written as +0 on output.
+ *
+ * BASES.  The FP64 entry points take the paper's coefficients (the normalisation of the
+ * Appendix recurrences).  The FP32 entry points take and return coefficients in the
+ * NORMALISED basis: M_hat_n^m = M_n^m * w_n^m and L_hat_n^m = L_n^m / w_n^m with
+ * w_n^m = sqrt((n+m)! (n-m)!).  (Raw coefficients and the factorials up to (2P-2)! leave
+ * the float range for P >= 19.)  sh_normalise_f64 / sh_denormalise_f64 convert.
+ *
+ * SHIFTS.  r = (output centre) - (input centre) for all three operations; for M2L this
+ * is r_AB = x_B - x_A of Section 2.1.  M2L needs 0 < |r| < inf; M2M and L2L accept r = 0
+ * (identity, truncated or zero-padded to the output order).
+ *
+ * MIXED ORDERS (Section 1.1).  1 <= p_in, p_out <= the context's max order.  M2L sums
+ * over every input degree k < p_in for every output degree n < p_out.  M2M output rows
+ * n >= p_in use the available input degrees; L2L output rows k >= p_in are zero.
+ *
+ * OWNERSHIP.  The caller owns every coefficient, shift and index array.  Batched calls
+ * take DEVICE pointers and are stream-ordered on the given HIP stream (NULL = the null
+ * stream); they return after enqueue.  Single-translation calls take HOST pointers and
+ * are synchronous.  The context owns its constant tables; it is never modified after
+ * sh_create, so any number of host threads may use it concurrently on distinct streams.
+ * Batched calls allocate nothing.
+ *
+ * DEVICE-SIDE ERRORS.  A batched M2L translation whose shift is zero or not finite writes
+ * NaN into its output solid and raises the context's device error flag; read and clear
+ * it with sh_device_error() after synchronising the stream.
+ */
+#ifndef SHFMM_H
+#define SHFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sh_ctx sh_ctx; /* opaque handle (Section 1.1: encapsulation by handles) */
+
+typedef enum {
+    SH_OK = 0,
+    SH_EINVAL = -1,  /* null pointer, negative count, bad stride, unknown op/dtype */
+    SH_EORDER = -2,  /* order outside [1, max order] */
+    SH_ESHIFT = -3,  /* M2L shift zero or not finite (host-checked calls) */
+    SH_ENOMEM = -4,  /* device allocation failed (sh_create only) */
+    SH_EDEVICE = -5, /* HIP runtime error, or no usable gfx950 device */
+    SH_EBUSY = -6    /* resource limit of a bounded call exceeded */
+} sh_status;
+
+enum { SH_M2M = 0, SH_M2L = 1, SH_L2L = 2 };  /* operations */
+enum { SH_F64 = 0, SH_F32 = 1 };              /* data types */
+#define SH_ACCUMULATE 1u /* add into the output instead of overwriting (Section 3.4 stores) */
+
+#define SH_MAX_ORDER 64
+
+/* Human-readable text of a status code.  Never NULL. */
+const char *sh_strerror(int status);
+
+/* Creates a context for orders 1..max_order on HIP device `device`: builds the swap
+ * matrices (Section 3.1, Appendix) and z-axis coefficients exactly on the host, rounds
+ * them once and uploads them.  *out receives the handle.  Errors: SH_EINVAL (out NULL),
+ * SH_EORDER (max_order outside [1, SH_MAX_ORDER]), SH_EDEVICE, SH_ENOMEM. */
+sh_status sh_create(sh_ctx **out, int max_order, int device);
+
+/* Releases a context and its device memory.  NULL is accepted. */
+void sh_destroy(sh_ctx *ctx);
+
+/* Max order and device of a context (-1 for NULL). */
+int sh_max_order(const sh_ctx *ctx);
+int sh_device(const sh_ctx *ctx);
+
+/* Returns the device error flag (0 = none, else the first failing status) of a context
+ * and clears it.  Synchronises the device. */
+int sh_device_error(sh_ctx *ctx);
+
+/* ---------------- batched translations (device pointers, stream-ordered) ----------------
+ * Translation i reads its shift at r[3i..3i+2], its input solid at in + i*ld_in
+ * (p_in(p_in+1) reals) and writes out + i*ld_out (p_out(p_out+1) reals).
+ * ld_in >= p_in(p_in+1), ld_out >= p_out(p_out+1).  count = 0 is a no-op.
+ * flags: 0 or SH_ACCUMULATE (accumulate assumes the output solids do not overlap).
+ * hip_stream: a hipStream_t, or NULL.
+ * Errors: SH_EINVAL, SH_EORDER, SH_EDEVICE (launch failure).
+ * Precision: FP64 results match the double-height sums of eq. (m2lkernels) to about
+ * 1e-14 per degree in the normalised basis; FP32 (normalised basis) to about 1e-5. */
+sh_status sh_m2l_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const double *r, const double *in, int64_t ld_in,
+                           double *out, int64_t ld_out, unsigned flags, void *hip_stream);
+sh_status sh_m2m_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const double *r, const double *in, int64_t ld_in,
+                           double *out, int64_t ld_out, unsigned flags, void *hip_stream);
+sh_status sh_l2l_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const double *r, const double *in, int64_t ld_in,
+                           double *out, int64_t ld_out, unsigned flags, void *hip_stream);
+sh_status sh_m2l_batch_f32(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const float *r, const float *in, int64_t ld_in,
+                           float *out, int64_t ld_out, unsigned flags, void *hip_stream);
+sh_status sh_m2m_batch_f32(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const float *r, const float *in, int64_t ld_in,
+                           float *out, int64_t ld_out, unsigned flags, void *hip_stream);
+sh_status sh_l2l_batch_f32(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                           const float *r, const float *in, int64_t ld_in,
+                           float *out, int64_t ld_out, unsigned flags, void *hip_stream);
+
+/* Generic form of the six calls above: op in {SH_M2M, SH_M2L, SH_L2L}, dtype in
+ * {SH_F64, SH_F32}; r, in, out point to reals of that dtype. */
+sh_status sh_translate_batch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out,
+                             int64_t count, const void *r, const void *in, int64_t ld_in,
+                             void *out, int64_t ld_out, unsigned flags, void *hip_stream);
+
+/* Indexed gather/scatter over resident pools (octree / serving use): translation i reads
+ * in_pool + src[i]*ld_in and writes out_pool + dst[i]*ld_out (device int64 index arrays,
+ * every index >= 0 and inside the caller's pools).  With SH_ACCUMULATE, dst indices must
+ * be unique within the call.  Errors as for the batched calls. */
+sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out,
+                               int64_t count, const void *r, const int64_t *src,
+                               const void *in_pool, int64_t ld_in, const int64_t *dst,
+                               void *out_pool, int64_t ld_out, unsigned flags,
+                               void *hip_stream);
+
+/* ---------------- single translation (host pointers, synchronous) ----------------
+ * The paper's statement of the problem: one input solid, one shift, one output solid.
+ * Errors: SH_EINVAL, SH_EORDER, SH_ESHIFT (M2L with r = 0 or non-finite r), SH_EDEVICE. */
+sh_status sh_m2l_f64(const sh_ctx *ctx, int p_in, int p_out, const double r[3],
+                     const double *M, double *L);
+sh_status sh_m2m_f64(const sh_ctx *ctx, int p_in, int p_out, const double r[3],
+                     const double *M, double *Mout);
+sh_status sh_l2l_f64(const sh_ctx *ctx, int p_in, int p_out, const double r[3],
+                     const double *L, double *Lout);
+sh_status sh_m2l_f32(const sh_ctx *ctx, int p_in, int p_out, const float r[3],
+                     const float *M, float *L);
+sh_status sh_m2m_f32(const sh_ctx *ctx, int p_in, int p_out, const float r[3],
+                     const float *M, float *Mout);
+sh_status sh_l2l_f32(const sh_ctx *ctx, int p_in, int p_out, const float r[3],
+                     const float *L, float *Lout);
+
+/* ---------------- baseline and neighbouring steps ----------------
+ * Direct double-height M2L (eq. m2lkernels, right) with S by the Appendix recurrence:
+ * the O(P^4) loop the paper benchmarks against (Section 4), FP64, same layout and
+ * arguments as sh_m2l_batch_f64. */
+sh_status sh_m2l_naive_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count,
+                                 const double *r, const double *in, int64_t ld_in,
+                                 double *out, int64_t ld_out, unsigned flags,
+                                 void *hip_stream);
+
+/* P2M on the device (eq. MLexpansions with the Appendix recurrence for R):
+ * M_n^m = sum_j q_j R_n^m(y_j - c) for `count` clusters of `npts` points each; cluster c
+ * has centre centres[3c..], points pts[3*npts*c ..] and charges q[npts*c ..]; output
+ * solid c at M + c*ldM.  FP64, device pointers, stream-ordered. */
+sh_status sh_p2m_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double *centres,
+                           int64_t npts, const double *pts, const double *q, double *M,
+                           int64_t ldM, void *hip_stream);
+
+/* ---------------- host-only helpers (no device needed) ----------------
+ * Dense (n+1)x(n+1) row-major swap matrix of degree n (0 <= n < SH_MAX_ORDER), rounded
+ * once from exact arithmetic.  which: 0 = F (M side, real parts), 1 = G (M side,
+ * imaginary parts), 2 = F_L (L side, real), 3 = G_L (L side, imaginary).
+ * normalised != 0 gives the normalised-basis matrix.  Errors: SH_EINVAL, SH_EORDER. */
+sh_status sh_swap_matrix_f64(int n, int which, int normalised, double *out);
+
+/* Scales solids between the paper's basis and the normalised basis, on the host:
+ * kind 0 = multipole-type (x w_n^m), 1 = local-type (/ w_n^m); sh_denormalise_f64 undoes
+ * it.  `count` solids of order P at stride ld, in place. */
+sh_status sh_normalise_f64(int kind, int P, int64_t count, double *solids, int64_t ld);
+sh_status sh_denormalise_f64(int kind, int P, int64_t count, double *solids, int64_t ld);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHFMM_H */

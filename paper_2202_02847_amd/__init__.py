@@ -1,0 +1,235 @@
+"""Python binding of the shfmm C ABI (``include/shfmm.h``): argument marshalling only.
+
+Every computation runs in the HIP library ``libshfmm.so`` built for gfx950 (see
+``build.py``); the functions here carry the C names and forward to them via ctypes.
+Device arrays are passed as torch tensors on the GPU (their ``data_ptr()``) or as raw
+integer addresses.  There is no CPU fallback: if the library is missing, importing
+works but every call raises ``LibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshfmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "shfmm.h")
+
+SH_OK, SH_EINVAL, SH_EORDER, SH_ESHIFT, SH_ENOMEM, SH_EDEVICE, SH_EBUSY = 0, -1, -2, -3, -4, -5, -6
+SH_M2M, SH_M2L, SH_L2L = 0, 1, 2
+SH_F64, SH_F32 = 0, 1
+SH_ACCUMULATE = 1
+SH_MAX_ORDER = 64
+OPS = {"m2m": SH_M2M, "m2l": SH_M2L, "l2l": SH_L2L}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class ShError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {sh_strerror(status)} ({status})")
+
+
+_lib = None
+
+_c_i32, _c_i64, _c_u32, _vp = ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_void_p
+_SIGS = {
+    "sh_strerror": (ctypes.c_char_p, [_c_i32]),
+    "sh_create": (_c_i32, [ctypes.POINTER(_vp), _c_i32, _c_i32]),
+    "sh_destroy": (None, [_vp]),
+    "sh_max_order": (_c_i32, [_vp]),
+    "sh_device": (_c_i32, [_vp]),
+    "sh_device_error": (_c_i32, [_vp]),
+    "sh_translate_batch": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
+    "sh_translate_indexed": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _vp, _c_i64, _vp, _vp, _c_i64, _c_u32, _vp]),
+    "sh_m2l_naive_batch_f64": (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
+    "sh_p2m_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _vp, _c_i64, _vp]),
+    "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
+    "sh_normalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
+    "sh_denormalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
+}
+for _op in ("m2l", "m2m", "l2l"):
+    for _dt in ("f64", "f32"):
+        _SIGS[f"sh_{_op}_batch_{_dt}"] = (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp])
+        _SIGS[f"sh_{_op}_{_dt}"] = (_c_i32, [_vp, _c_i32, _c_i32, _vp, _vp, _vp])
+
+
+def lib():
+    """The loaded ctypes library (raises LibraryMissing if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Names of every function the C header declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(sh_\w+)\s*\(", text, re.M)))
+
+
+def sh_strerror(status: int) -> str:
+    return lib().sh_strerror(int(status)).decode()
+
+
+def _check(st: int, where: str) -> None:
+    if st != SH_OK:
+        raise ShError(st, where)
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover - torch without GPU
+            pass
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Context:
+    """Owning wrapper of an ``sh_ctx*`` (sh_create / sh_destroy)."""
+
+    def __init__(self, max_order: int = 32, device: int = 0):
+        h = _vp()
+        _check(lib().sh_create(ctypes.byref(h), int(max_order), int(device)), "sh_create")
+        self._h = h
+        self.max_order = max_order
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_error(self) -> int:
+        return lib().sh_device_error(self._h)
+
+
+def sh_create(max_order: int = 32, device: int = 0) -> Context:
+    return Context(max_order, device)
+
+
+def sh_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def sh_device_error(ctx: Context) -> int:
+    return ctx.device_error()
+
+
+def sh_max_order(ctx) -> int:
+    return lib().sh_max_order(_h(ctx))
+
+
+def sh_device(ctx) -> int:
+    return lib().sh_device(_h(ctx))
+
+
+def _h(ctx):
+    return ctx.handle if isinstance(ctx, Context) else ctx
+
+
+def sh_translate_batch(ctx, op, dtype, p_in, p_out, count, r, inp, ld_in, out, ld_out, flags=0, stream=None):
+    _check(lib().sh_translate_batch(_h(ctx), OPS.get(op, op), dtype, p_in, p_out, count, _ptr(r), _ptr(inp),
+                                    ld_in, _ptr(out), ld_out, flags, _stream(stream)), "sh_translate_batch")
+
+
+def sh_translate_indexed(ctx, op, dtype, p_in, p_out, count, r, src, in_pool, ld_in, dst, out_pool, ld_out,
+                         flags=0, stream=None):
+    _check(lib().sh_translate_indexed(_h(ctx), OPS.get(op, op), dtype, p_in, p_out, count, _ptr(r), _ptr(src),
+                                      _ptr(in_pool), ld_in, _ptr(dst), _ptr(out_pool), ld_out, flags,
+                                      _stream(stream)), "sh_translate_indexed")
+
+
+def _make_batch(name):
+    def f(ctx, p_in, p_out, count, r, inp, ld_in, out, ld_out, flags=0, stream=None):
+        _check(getattr(lib(), name)(_h(ctx), p_in, p_out, count, _ptr(r), _ptr(inp), ld_in, _ptr(out), ld_out,
+                                    flags, _stream(stream)), name)
+    f.__name__ = name
+    f.__doc__ = f"Forwards to the C function {name} (device pointers, stream-ordered)."
+    return f
+
+
+def _make_single(name, dtype):
+    def f(ctx, p_in, p_out, r, C):
+        """Single translation on host arrays (synchronous); returns the output solid."""
+        r = np.ascontiguousarray(r, dtype=dtype)
+        C = np.ascontiguousarray(C, dtype=dtype)
+        out = np.zeros(p_out * (p_out + 1), dtype)
+        _check(getattr(lib(), name)(_h(ctx), p_in, p_out, r.ctypes.data, C.ctypes.data, out.ctypes.data), name)
+        return out
+    f.__name__ = name
+    return f
+
+
+for _op in ("m2l", "m2m", "l2l"):
+    for _dt, _npdt in (("f64", np.float64), ("f32", np.float32)):
+        globals()[f"sh_{_op}_batch_{_dt}"] = _make_batch(f"sh_{_op}_batch_{_dt}")
+        globals()[f"sh_{_op}_{_dt}"] = _make_single(f"sh_{_op}_{_dt}", _npdt)
+sh_m2l_naive_batch_f64 = _make_batch("sh_m2l_naive_batch_f64")
+
+
+def sh_p2m_batch_f64(ctx, P, count, centres, npts, pts, q, M, ldM, stream=None):
+    _check(lib().sh_p2m_batch_f64(_h(ctx), P, count, _ptr(centres), npts, _ptr(pts), _ptr(q), _ptr(M), ldM,
+                                  _stream(stream)), "sh_p2m_batch_f64")
+
+
+def sh_swap_matrix_f64(n: int, which: int, normalised: bool = False) -> np.ndarray:
+    out = np.zeros((n + 1, n + 1))
+    _check(lib().sh_swap_matrix_f64(n, which, int(bool(normalised)), out.ctypes.data), "sh_swap_matrix_f64")
+    return out
+
+
+def sh_normalise_f64(kind: int, P: int, solids: np.ndarray) -> np.ndarray:
+    a = np.array(solids, dtype=np.float64, copy=True, order="C")
+    a2 = a.reshape(-1, a.shape[-1])
+    _check(lib().sh_normalise_f64(kind, P, a2.shape[0], a2.ctypes.data, a2.shape[1]), "sh_normalise_f64")
+    return a
+
+
+def sh_denormalise_f64(kind: int, P: int, solids: np.ndarray) -> np.ndarray:
+    a = np.array(solids, dtype=np.float64, copy=True, order="C")
+    a2 = a.reshape(-1, a.shape[-1])
+    _check(lib().sh_denormalise_f64(kind, P, a2.shape[0], a2.ctypes.data, a2.shape[1]), "sh_denormalise_f64")
+    return a

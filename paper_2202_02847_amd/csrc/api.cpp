@@ -1,0 +1,401 @@
+// C ABI of the translation library: context management, argument validation and
+// kernel dispatch.  No C++ exception crosses this boundary (Section 1.1: exception
+// safe); every entry point returns a status code.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/shfmm.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+struct sh_ctx {
+    int device = -1;
+    int max_order = 0;
+    void *dev_mem = nullptr;     // one allocation holding every table
+    int *err_flag = nullptr;     // device int
+    shfmm::DevTables tabs{};
+};
+
+namespace {
+
+using shfmm::TransArgs;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool valid_op(int op) { return op == SH_M2M || op == SH_M2L || op == SH_L2L; }
+bool valid_dtype(int d) { return d == SH_F64 || d == SH_F32; }
+
+sh_status check_common(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                       int64_t ld_in, int64_t ld_out, unsigned flags)
+{
+    if (!ctx || !valid_op(op) || !valid_dtype(dtype) || count < 0 || (flags & ~SH_ACCUMULATE))
+        return SH_EINVAL;
+    if (p_in < 1 || p_out < 1 || p_in > ctx->max_order || p_out > ctx->max_order) return SH_EORDER;
+    if (ld_in < (int64_t)p_in * (p_in + 1) || ld_out < (int64_t)p_out * (p_out + 1)) return SH_EINVAL;
+    return SH_OK;
+}
+
+sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                 const void *r, const int64_t *src, const void *in, int64_t ld_in,
+                 const int64_t *dst, void *out, int64_t ld_out, unsigned flags, void *stream)
+{
+    sh_status st = check_common(ctx, op, dtype, p_in, p_out, count, ld_in, ld_out, flags);
+    if (st != SH_OK) return st;
+    if (count == 0) return SH_OK;
+    if (!r || !in || !out) return SH_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    TransArgs a;
+    a.op = op;
+    a.p_in = p_in;
+    a.p_out = p_out;
+    a.count = count;
+    a.r = r;
+    a.in = in;
+    a.ld_in = ld_in;
+    a.out = out;
+    a.ld_out = ld_out;
+    a.src = src;
+    a.dst = dst;
+    a.flags = flags;
+    a.err = ctx->err_flag;
+    const bool f32 = dtype == SH_F32;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (shfmm::lpt_available(op, f32, p_in, p_out))
+        e = shfmm::launch_lpt(ctx->tabs, a, f32, s);
+    else
+        e = shfmm::launch_general(ctx->tabs, a, f32, s);
+    return e == hipSuccess ? SH_OK : SH_EDEVICE;
+}
+
+template <typename Real>
+sh_status single(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, const Real r[3],
+                 const Real *C, Real *out)
+{
+    if (!ctx || !r || !C || !out) return SH_EINVAL;
+    if (p_in < 1 || p_out < 1 || p_in > ctx->max_order || p_out > ctx->max_order) return SH_EORDER;
+    const double x = r[0], y = r[1], z = r[2];
+    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return SH_ESHIFT;
+    if (op == SH_M2L && x == 0 && y == 0 && z == 0) return SH_ESHIFT;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    const size_t nin = (size_t)p_in * (p_in + 1), nout = (size_t)p_out * (p_out + 1);
+    Real *d = nullptr;
+    if (hipMalloc(&d, sizeof(Real) * (3 + nin + nout)) != hipSuccess) return SH_ENOMEM;
+    sh_status st = SH_OK;
+    if (hipMemcpy(d, r, 3 * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d + 3, C, nin * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess)
+        st = SH_EDEVICE;
+    if (st == SH_OK)
+        st = launch(ctx, op, dtype, p_in, p_out, 1, d, nullptr, d + 3, (int64_t)nin, nullptr,
+                    d + 3 + nin, (int64_t)nout, 0, nullptr);
+    if (st == SH_OK && hipMemcpy(out, d + 3 + nin, nout * sizeof(Real), hipMemcpyDeviceToHost) != hipSuccess)
+        st = SH_EDEVICE;
+    (void)hipFree(d);
+    return st;
+}
+
+long double weight(int n, int m)
+{
+    long double f = 1;
+    for (int j = 2; j <= n + m; ++j) f *= j;
+    long double g = 1;
+    for (int j = 2; j <= n - m; ++j) g *= j;
+    return sqrtl(f * g);
+}
+
+sh_status scale_solids(int kind, int P, int64_t count, double *solids, int64_t ld, bool inverse)
+{
+    if ((kind != 0 && kind != 1) || !solids || count < 0) return SH_EINVAL;
+    if (P < 1 || P > SH_MAX_ORDER) return SH_EORDER;
+    if (ld < (int64_t)P * (P + 1)) return SH_EINVAL;
+    std::vector<double> f((size_t)P * (P + 1));
+    for (int n = 0; n < P; ++n)
+        for (int m = 0; m <= n; ++m) {
+            long double w = weight(n, m);
+            bool mult = (kind == 0) != inverse;  // M-type: x w; L-type: / w
+            double v = (double)(mult ? w : 1.0L / w);
+            f[n * (n + 1) + 2 * m] = v;
+            f[n * (n + 1) + 2 * m + 1] = v;
+        }
+    for (int64_t c = 0; c < count; ++c)
+        for (size_t i = 0; i < f.size(); ++i) solids[c * ld + (int64_t)i] *= f[i];
+    return SH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sh_strerror(int status)
+{
+    switch (status) {
+    case SH_OK: return "success";
+    case SH_EINVAL: return "invalid argument";
+    case SH_EORDER: return "expansion order out of range";
+    case SH_ESHIFT: return "invalid shift vector (zero or non-finite M2L shift)";
+    case SH_ENOMEM: return "device memory allocation failed";
+    case SH_EDEVICE: return "HIP device or launch error";
+    case SH_EBUSY: return "resource limit exceeded";
+    default: return "unknown status";
+    }
+}
+
+sh_status sh_create(sh_ctx **out, int max_order, int device)
+{
+    if (!out) return SH_EINVAL;
+    *out = nullptr;
+    if (max_order < 1 || max_order > SH_MAX_ORDER) return SH_EORDER;
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SH_EDEVICE;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SH_EDEVICE;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SH_EDEVICE;
+        shfmm::HostTables ht;
+        shfmm::build_tables(max_order, ht);
+        DeviceGuard g(device);
+        if (!g.ok) return SH_EDEVICE;
+        // layout: swap64[4] | z64[3] | swap32[4] | z32[3] | err flag, each 256-byte aligned
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        size_t total = 0;
+        std::vector<size_t> offs;
+        for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.swap64[k].size() * 8); }
+        for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z64[k].size() * 8); }
+        for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.swap32[k].size() * 4); }
+        for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z32[k].size() * 4); }
+        offs.push_back(total);
+        total += 256;
+        void *mem = nullptr;
+        if (hipMalloc(&mem, total) != hipSuccess) return SH_ENOMEM;
+        char *base = static_cast<char *>(mem);
+        bool ok = true;
+        int idx = 0;
+        sh_ctx *c = new (std::nothrow) sh_ctx;
+        if (!c) {
+            (void)hipFree(mem);
+            return SH_ENOMEM;
+        }
+        for (int k = 0; k < 4; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.swap64[k].data(), ht.swap64[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.swap64[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 3; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.z64[k].data(), ht.z64[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.z64[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 4; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.swap32[k].data(), ht.swap32[k].size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.swap32[k] = reinterpret_cast<const float *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 3; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.z32[k].data(), ht.z32[k].size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.z32[k] = reinterpret_cast<const float *>(base + offs[idx]);
+        }
+        c->err_flag = reinterpret_cast<int *>(base + offs[idx]);
+        ok &= hipMemset(c->err_flag, 0, sizeof(int)) == hipSuccess;
+        ok &= hipDeviceSynchronize() == hipSuccess;
+        c->tabs.P = max_order;
+        c->device = device;
+        c->max_order = max_order;
+        c->dev_mem = mem;
+        if (!ok) {
+            (void)hipFree(mem);
+            delete c;
+            return SH_EDEVICE;
+        }
+        *out = c;
+        return SH_OK;
+    } catch (const std::bad_alloc &) {
+        return SH_ENOMEM;
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+void sh_destroy(sh_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->dev_mem) (void)hipFree(ctx->dev_mem);
+    }
+    delete ctx;
+}
+
+int sh_max_order(const sh_ctx *ctx) { return ctx ? ctx->max_order : -1; }
+int sh_device(const sh_ctx *ctx) { return ctx ? ctx->device : -1; }
+
+int sh_device_error(sh_ctx *ctx)
+{
+    if (!ctx) return SH_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok || hipDeviceSynchronize() != hipSuccess) return SH_EDEVICE;
+    int v = 0;
+    if (hipMemcpy(&v, ctx->err_flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SH_EDEVICE;
+    if (v != 0 && hipMemset(ctx->err_flag, 0, sizeof(int)) != hipSuccess) return SH_EDEVICE;
+    return v;
+}
+
+#define SH_BATCH(NAME, OP, DT, T)                                                                  \
+    sh_status NAME(const sh_ctx *ctx, int p_in, int p_out, int64_t count, const T *r, const T *in,  \
+                   int64_t ld_in, T *out, int64_t ld_out, unsigned flags, void *hip_stream)         \
+    {                                                                                              \
+        try {                                                                                      \
+            return launch(ctx, OP, DT, p_in, p_out, count, r, nullptr, in, ld_in, nullptr, out,    \
+                          ld_out, flags, hip_stream);                                              \
+        } catch (...) {                                                                            \
+            return SH_EINVAL;                                                                      \
+        }                                                                                          \
+    }
+SH_BATCH(sh_m2l_batch_f64, SH_M2L, SH_F64, double)
+SH_BATCH(sh_m2m_batch_f64, SH_M2M, SH_F64, double)
+SH_BATCH(sh_l2l_batch_f64, SH_L2L, SH_F64, double)
+SH_BATCH(sh_m2l_batch_f32, SH_M2L, SH_F32, float)
+SH_BATCH(sh_m2m_batch_f32, SH_M2M, SH_F32, float)
+SH_BATCH(sh_l2l_batch_f32, SH_L2L, SH_F32, float)
+#undef SH_BATCH
+
+sh_status sh_translate_batch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                             const void *r, const void *in, int64_t ld_in, void *out, int64_t ld_out,
+                             unsigned flags, void *hip_stream)
+{
+    try {
+        return launch(ctx, op, dtype, p_in, p_out, count, r, nullptr, in, ld_in, nullptr, out, ld_out,
+                      flags, hip_stream);
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                               const void *r, const int64_t *src, const void *in_pool, int64_t ld_in,
+                               const int64_t *dst, void *out_pool, int64_t ld_out, unsigned flags,
+                               void *hip_stream)
+{
+    if (count > 0 && (!src || !dst)) return SH_EINVAL;
+    try {
+        return launch(ctx, op, dtype, p_in, p_out, count, r, src, in_pool, ld_in, dst, out_pool, ld_out,
+                      flags, hip_stream);
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+#define SH_SINGLE(NAME, OP, DT, T)                                                                 \
+    sh_status NAME(const sh_ctx *ctx, int p_in, int p_out, const T r[3], const T *C, T *out)       \
+    {                                                                                              \
+        try {                                                                                      \
+            return single<T>(ctx, OP, DT, p_in, p_out, r, C, out);                                 \
+        } catch (...) {                                                                            \
+            return SH_EINVAL;                                                                      \
+        }                                                                                          \
+    }
+SH_SINGLE(sh_m2l_f64, SH_M2L, SH_F64, double)
+SH_SINGLE(sh_m2m_f64, SH_M2M, SH_F64, double)
+SH_SINGLE(sh_l2l_f64, SH_L2L, SH_F64, double)
+SH_SINGLE(sh_m2l_f32, SH_M2L, SH_F32, float)
+SH_SINGLE(sh_m2m_f32, SH_M2M, SH_F32, float)
+SH_SINGLE(sh_l2l_f32, SH_L2L, SH_F32, float)
+#undef SH_SINGLE
+
+sh_status sh_m2l_naive_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count, const double *r,
+                                 const double *in, int64_t ld_in, double *out, int64_t ld_out,
+                                 unsigned flags, void *hip_stream)
+{
+    sh_status st = check_common(ctx, SH_M2L, SH_F64, p_in, p_out, count, ld_in, ld_out, flags);
+    if (st != SH_OK) return st;
+    if (count == 0) return SH_OK;
+    if (!r || !in || !out) return SH_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    TransArgs a{};
+    a.op = SH_M2L;
+    a.p_in = p_in;
+    a.p_out = p_out;
+    a.count = count;
+    a.r = r;
+    a.in = in;
+    a.ld_in = ld_in;
+    a.out = out;
+    a.ld_out = ld_out;
+    a.flags = flags;
+    a.err = ctx->err_flag;
+    return shfmm::launch_m2l_naive(a, reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess ? SH_OK
+                                                                                                : SH_EDEVICE;
+}
+
+sh_status sh_p2m_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double *centres, int64_t npts,
+                           const double *pts, const double *q, double *M, int64_t ldM, void *hip_stream)
+{
+    if (!ctx || count < 0 || npts < 0) return SH_EINVAL;
+    if (P < 1 || P > ctx->max_order) return SH_EORDER;
+    if (ldM < (int64_t)P * (P + 1)) return SH_EINVAL;
+    if (count == 0) return SH_OK;
+    if (!centres || !M || (npts > 0 && (!pts || !q))) return SH_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    return shfmm::launch_p2m(P, count, centres, npts, pts, q, M, ldM,
+                             reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess
+               ? SH_OK
+               : SH_EDEVICE;
+}
+
+sh_status sh_swap_matrix_f64(int n, int which, int normalised, double *out)
+{
+    if (!out || which < 0 || which > 3) return SH_EINVAL;
+    if (n < 0 || n >= SH_MAX_ORDER) return SH_EORDER;
+    try {
+        if (!normalised) {
+            for (int m = 0; m <= n; ++m)
+                for (int l = 0; l <= n; ++l)
+                    out[m * (n + 1) + l] = shfmm::swap_entry_f64(n, (shfmm::SwapKind)which, m, l);
+        } else {
+            std::vector<long double> t((size_t)(n + 1) * (n + 1));
+            shfmm::swap_matrix_ld(n, (shfmm::SwapKind)which, true, t.data());
+            for (size_t i = 0; i < t.size(); ++i) out[i] = (double)t[i];
+        }
+        return SH_OK;
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+sh_status sh_normalise_f64(int kind, int P, int64_t count, double *solids, int64_t ld)
+{
+    try {
+        return scale_solids(kind, P, count, solids, ld, false);
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+sh_status sh_denormalise_f64(int kind, int P, int64_t count, double *solids, int64_t ld)
+{
+    try {
+        return scale_solids(kind, P, count, solids, ld, true);
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device-side definitions shared by the translation kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace shfmm {
+
+// Constant tables resident in device memory (built and uploaded once per context).
+// Swap matrices: dense (n+1)x(n+1) row-major per degree n at offset n(n+1)(2n+1)/6,
+// kinds F, G (M side), FL, GL (L side).  z coefficients: column m block at
+// sum_{j<m} (P-j)^2, entry [out-m][in-m] with row length P-m, P = table order.
+struct DevTables {
+    const double *swap64[4];
+    const float *swap32[4];
+    const double *z64[3];
+    const float *z32[3];
+    int P;
+};
+
+template <typename Real>
+struct Tab;
+template <>
+struct Tab<double> {
+    __device__ static const double *swap(const DevTables &t, int k) { return t.swap64[k]; }
+    __device__ static const double *z(const DevTables &t, int k) { return t.z64[k]; }
+};
+template <>
+struct Tab<float> {
+    __device__ static const float *swap(const DevTables &t, int k) { return t.swap32[k]; }
+    __device__ static const float *z(const DevTables &t, int k) { return t.z32[k]; }
+};
+
+enum { OP_M2M = 0, OP_M2L = 1, OP_L2L = 2 };
+enum { SW_F = 0, SW_G = 1, SW_FL = 2, SW_GL = 3 };
+
+__host__ __device__ constexpr int swap_off(int n) { return n * (n + 1) * (2 * n + 1) / 6; }
+__host__ __device__ constexpr int solid_pos(int n, int m) { return n * (n + 1) + 2 * m; }
+// start of column block m of a z-coefficient table of order P: sum_{j<m} (P-j)^2
+__host__ __device__ constexpr int64_t z_col_off(int P, int m)
+{
+    return ((int64_t)P * (P + 1) * (2 * P + 1) - (int64_t)(P - m) * (P - m + 1) * (2 * (P - m) + 1)) / 6;
+}
+
+// Geometry of a shift (Section 3.4, step 1): |r|, rho = sqrt(x^2+y^2) and the two
+// z-rotation angles, without trigonometric functions:
+//   cos a = y/rho, sin a = x/rho  (cos a = 1, sin a = 0 when x = y = 0)
+//   cos b = z/|r|, sin b = -rho/|r|
+// Rotating by a, swapping x<->z, rotating by b and swapping again sends r to (0,0,|r|).
+struct Geometry {
+    double R, s;  // |r| and 1/|r|
+    double ca, sa, cb, sb;
+    int valid;    // 0: r = 0; -1: not finite; 1: ok
+};
+
+__device__ __forceinline__ Geometry shift_geometry(double x, double y, double z)
+{
+    Geometry g;
+    const double rho2 = x * x + y * y;
+    const double r2 = rho2 + z * z;
+    const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r2);
+    g.valid = !finite ? -1 : (r2 > 0.0 ? 1 : 0);
+    const double R = sqrt(r2);
+    const double rho = sqrt(rho2);
+    g.R = R;
+    g.s = (g.valid == 1) ? 1.0 / R : 0.0;
+    if (rho > 0.0) {
+        const double ir = 1.0 / rho;
+        g.ca = y * ir;
+        g.sa = x * ir;
+    } else {
+        g.ca = 1.0;
+        g.sa = 0.0;
+    }
+    g.cb = (g.valid == 1) ? z * g.s : 1.0;
+    g.sb = (g.valid == 1) ? -rho * g.s : 0.0;
+    return g;
+}
+
+// Vector (not scalar-cache) atomic raise of the context's device error flag.
+__device__ __forceinline__ void raise_device_error(int *flag, int code)
+{
+    if (flag) atomicCAS(flag, 0, code);
+}
+
+}  // namespace shfmm

@@ -1,0 +1,182 @@
+// Neighbouring kernels of the translation path:
+//   * the direct O(P^4) double-height M2L (eq. m2lkernels, right), the baseline the paper
+//     measures its scheme against (Section 4), with S by the Appendix recurrences;
+//   * P2M (eq. MLexpansions: M_n^m = sum_j q_j R_n^m(y_j - x_A)), R by the Appendix
+//     recurrences, used to build multipole inputs on the device.
+#include "kernels.hpp"
+
+namespace shfmm {
+
+namespace {
+
+__device__ __forceinline__ int tri_row_aux(int c)
+{
+    int n = (int)((sqrtf(8.0f * (float)c + 1.0f) - 1.0f) * 0.5f);
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    while (n * (n + 1) / 2 > c) --n;
+    return n;
+}
+
+// one wavefront per translation; S_j^i(r) for j < ps in LDS, M staged in LDS,
+// lanes own outputs (n, m) and run the k, l double loop.
+__global__ __launch_bounds__(64) void k_m2l_naive(TransArgs a)
+{
+    extern __shared__ double sm[];
+    const int p_in = a.p_in, p_out = a.p_out;
+    const int ps = p_in + p_out - 1;
+    double *S = sm;                      // ps(ps+1)
+    double *M = S + ps * (ps + 1);       // p_in(p_in+1)
+    const int lane = threadIdx.x;
+    const double *rr = reinterpret_cast<const double *>(a.r);
+    const bool acc = (a.flags & 1u) != 0;
+    for (int64_t t = blockIdx.x; t < a.count; t += gridDim.x) {
+        const int64_t si = a.src ? a.src[t] : t;
+        const int64_t di = a.dst ? a.dst[t] : t;
+        const double *in = reinterpret_cast<const double *>(a.in) + si * a.ld_in;
+        double *out = reinterpret_cast<double *>(a.out) + di * a.ld_out;
+        const double x = rr[3 * t], y = rr[3 * t + 1], z = rr[3 * t + 2];
+        const double r2 = x * x + y * y + z * z;
+        if (!(r2 > 0.0) || !isfinite(r2)) {
+            for (int i = lane; i < p_out * (p_out + 1); i += 64) out[i] = NAN;
+            if (lane == 0) raise_device_error(a.err, -3);
+            continue;
+        }
+        for (int i = lane; i < p_in * (p_in + 1); i += 64) M[i] = in[i];
+        // diagonal S_n^n = (2n-1)(x+iy)/|r|^2 S_{n-1}^{n-1}
+        if (lane == 0) {
+            double pr = 1.0 / sqrt(r2), pi = 0.0;
+            S[0] = pr;
+            S[1] = 0.0;
+            for (int n = 1; n < ps; ++n) {
+                const double f = (2 * n - 1) / r2;
+                const double nr = f * (x * pr - y * pi), ni = f * (x * pi + y * pr);
+                pr = nr;
+                pi = ni;
+                S[solid_pos(n, n)] = pr;
+                S[solid_pos(n, n) + 1] = pi;
+            }
+        }
+        __syncthreads();
+        // columns: |r|^2 S_n^m = (2n-1) z S_{n-1}^m - ((n-1)^2 - m^2) S_{n-2}^m
+        for (int m = lane; m < ps; m += 64) {
+            for (int n = m + 1; n < ps; ++n)
+                for (int c = 0; c < 2; ++c) {
+                    const double s1 = S[solid_pos(n - 1, m) + c];
+                    const double s2 = (n - 2 >= m) ? S[solid_pos(n - 2, m) + c] : 0.0;
+                    S[solid_pos(n, m) + c] = ((2 * n - 1) * z * s1 - ((double)(n - 1) * (n - 1) - (double)m * m) * s2) / r2;
+                }
+        }
+        __syncthreads();
+        const int tri = p_out * (p_out + 1) / 2;
+        for (int c = lane; c < tri; c += 64) {
+            const int n = tri_row_aux(c);
+            const int m = c - n * (n + 1) / 2;
+            double sr = 0.0, sI = 0.0;
+            for (int k = 0; k < p_in; ++k)
+                for (int l = -k; l <= k; ++l) {
+                    const int al = l < 0 ? -l : l;
+                    double mr = M[solid_pos(k, al)], mi = al ? M[solid_pos(k, al) + 1] : 0.0;
+                    if (l < 0) {
+                        const double sg = (al & 1) ? -1.0 : 1.0;
+                        mr *= sg;
+                        mi *= -sg;
+                    }
+                    const int j = n + k, i = m + l;
+                    const int ai = i < 0 ? -i : i;
+                    double tr = S[solid_pos(j, ai)], ti = S[solid_pos(j, ai) + 1];
+                    if (i < 0) {
+                        const double sg = (ai & 1) ? -1.0 : 1.0;
+                        tr *= sg;
+                        ti *= -sg;
+                    }
+                    sr += mr * tr + mi * ti;   // conj(M) * S
+                    sI += mr * ti - mi * tr;
+                }
+            const double sg = (n & 1) ? -1.0 : 1.0;
+            double vr = sg * sr, vi = m ? sg * sI : 0.0;
+            if (acc) {
+                vr += out[solid_pos(n, m)];
+                if (m) vi += out[solid_pos(n, m) + 1];
+            }
+            out[solid_pos(n, m)] = vr;
+            out[solid_pos(n, m) + 1] = vi;
+        }
+        __syncthreads();
+    }
+}
+
+// one wavefront per cluster; lane m accumulates column m of sum_j q_j R(y_j - c)
+__global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *centres, int64_t npts,
+                                            const double *pts, const double *q, double *Mout, int64_t ldM)
+{
+    extern __shared__ double accm[];  // P(P+1)
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < count; c += gridDim.x) {
+        for (int i = lane; i < P * (P + 1); i += 64) accm[i] = 0.0;
+        __syncthreads();
+        const double cx = centres[3 * c], cy = centres[3 * c + 1], cz = centres[3 * c + 2];
+        for (int64_t j = 0; j < npts; ++j) {
+            const double *pj = pts + 3 * (npts * c + j);
+            const double x = pj[0] - cx, y = pj[1] - cy, z = pj[2] - cz;
+            const double r2 = x * x + y * y + z * z;
+            const double qj = q[npts * c + j];
+            for (int m = lane; m < P; m += 64) {
+                // R_m^m = prod_{i=1}^{m} (x+iy)/(2i)
+                double dr = 1.0, di = 0.0;
+                for (int i = 1; i <= m; ++i) {
+                    const double nr = (x * dr - y * di) / (2 * i), ni = (x * di + y * dr) / (2 * i);
+                    dr = nr;
+                    di = ni;
+                }
+                // (n^2 - m^2) R_n^m = (2n-1) z R_{n-1}^m - |r|^2 R_{n-2}^m
+                double ar = dr, ai = di, br = 0.0, bi = 0.0;  // R_{n-1}, R_{n-2}
+                accm[solid_pos(m, m)] += qj * ar;
+                accm[solid_pos(m, m) + 1] += qj * ai;
+                for (int n = m + 1; n < P; ++n) {
+                    const double d = (double)n * n - (double)m * m;
+                    const double cr = ((2 * n - 1) * z * ar - r2 * br) / d;
+                    const double ci = ((2 * n - 1) * z * ai - r2 * bi) / d;
+                    br = ar;
+                    bi = ai;
+                    ar = cr;
+                    ai = ci;
+                    accm[solid_pos(n, m)] += qj * ar;
+                    accm[solid_pos(n, m) + 1] += qj * ai;
+                }
+            }
+        }
+        __syncthreads();
+        double *Mo = Mout + c * ldM;
+        for (int i = lane; i < P * (P + 1); i += 64) {
+            int n = (int)((sqrtf(4.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+            while ((n + 1) * (n + 2) <= i) ++n;
+            while (n * (n + 1) > i) --n;
+            Mo[i] = (i == n * (n + 1) + 1) ? 0.0 : accm[i];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_m2l_naive(const TransArgs &a, hipStream_t s)
+{
+    if (a.count <= 0) return hipSuccess;
+    const int ps = a.p_in + a.p_out - 1;
+    const size_t smem = (size_t)(ps * (ps + 1) + a.p_in * (a.p_in + 1)) * sizeof(double);
+    const int64_t grid64 = a.count < (1 << 20) ? a.count : (1 << 20);
+    hipLaunchKernelGGL(k_m2l_naive, dim3((unsigned)grid64), dim3(64), smem, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2m(int P, int64_t count, const double *centres, int64_t npts, const double *pts,
+                      const double *q, double *M, int64_t ldM, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const size_t smem = (size_t)P * (P + 1) * sizeof(double);
+    const int64_t grid64 = count < (1 << 20) ? count : (1 << 20);
+    hipLaunchKernelGGL(k_p2m, dim3((unsigned)grid64), dim3(64), smem, s, P, count, centres, npts, pts, q, M, ldM);
+    return hipGetLastError();
+}
+
+}  // namespace shfmm

@@ -1,0 +1,254 @@
+// General rotation-based translation kernel: one wavefront per translation, any
+// input/output orders up to the table order, FP64 (paper basis) or FP32 (normalised
+// basis).  Lanes own output coefficients (n, m); the solid lives in LDS.
+//
+// Steps (Section 3.4, "Summary: The Entire Algorithm"; M2M/L2L by the same skeleton):
+//   1. geometry of the shift, powers e^{im a}, e^{im b}, |r|^{+-n} (no trigonometry)
+//   2. rows of the input: scale, rotate by a, swap x<->z, rotate by b, swap again
+//   3. columns: the z-axis step with unit shift (M2L: Hankel of factorials, eq. zm2l-matrix;
+//      M2M/L2L: Toeplitz of 1/j!), signs folded into the coefficient table
+//   4. rows of the output: swap, rotate by -b, swap, rotate by -a, unscale, store
+// The M-side swap uses F, G; the L-side uses FL, GL (L -> B L of eq. swaptransform).
+#include "kernels.hpp"
+
+namespace shfmm {
+
+namespace {
+
+__device__ __forceinline__ int tri_row(int c)
+{
+    int n = (int)((sqrtf(8.0f * (float)c + 1.0f) - 1.0f) * 0.5f);
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    while (n * (n + 1) / 2 > c) --n;
+    return n;
+}
+
+// degree n of the real at index i of a solid (row n occupies [n(n+1), (n+1)(n+2)))
+__device__ __forceinline__ int solid_row(int i)
+{
+    int n = (int)((sqrtf(4.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+    while ((n + 1) * (n + 2) <= i) ++n;
+    while (n * (n + 1) > i) --n;
+    return n;
+}
+
+// y <- swap(x) on rows [0, rows): Re by Tre, Im by Tim (chequerboard: only every other l).
+template <typename Real>
+__device__ __forceinline__ void swap_rows(const Real *__restrict__ Tre, const Real *__restrict__ Tim,
+                                          const Real *x, Real *y, int rows, int lane)
+{
+    const int tri = rows * (rows + 1) / 2;
+    for (int c = lane; c < tri; c += 64) {
+        const int n = tri_row(c);
+        const int m = c - n * (n + 1) / 2;
+        const Real *fr = Tre + swap_off(n) + m * (n + 1);
+        const Real *gr = Tim + swap_off(n) + m * (n + 1);
+        const Real *xr = x + solid_pos(n, 0);
+        Real yre = 0, yim = 0;
+        for (int l = (m + n) & 1; l <= n; l += 2) yre += fr[l] * xr[2 * l];
+        for (int l = ((m + n) & 1) ^ 1; l <= n; l += 2) yim += gr[l] * xr[2 * l + 1];
+        y[solid_pos(n, m)] = yre;
+        y[solid_pos(n, m) + 1] = yim;
+    }
+}
+
+// x <- x * (er + i*sgn*ei)[m] on rows [0, rows)
+template <typename Real>
+__device__ __forceinline__ void zrot_rows(Real *x, const Real *er, const Real *ei, Real sgn, int rows, int lane)
+{
+    const int tri = rows * (rows + 1) / 2;
+    for (int c = lane; c < tri; c += 64) {
+        const int n = tri_row(c);
+        const int m = c - n * (n + 1) / 2;
+        const Real a = x[solid_pos(n, m)], b = x[solid_pos(n, m) + 1];
+        const Real cr = er[m], ci = sgn * ei[m];
+        x[solid_pos(n, m)] = a * cr - b * ci;
+        x[solid_pos(n, m) + 1] = a * ci + b * cr;
+    }
+}
+
+template <typename Real, int OP>
+__global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int p_in = a.p_in, p_out = a.p_out;
+    const int Pm = p_in > p_out ? p_in : p_out;
+    const int S = Pm * (Pm + 1);
+    Real *A = reinterpret_cast<Real *>(smem_raw);
+    Real *B = A + S;
+    Real *ear = B + S;
+    Real *eai = ear + Pm;
+    Real *ebr = eai + Pm;
+    Real *ebi = ebr + Pm;
+    Real *sc_in = ebi + Pm;
+    Real *sc_out = sc_in + Pm;
+    const int lane = threadIdx.x;
+
+    const int fw = (OP == OP_L2L) ? SW_FL : SW_F;
+    const int bw = (OP == OP_M2M) ? SW_F : SW_FL;
+    const Real *Ffw = Tab<Real>::swap(tab, fw), *Gfw = Tab<Real>::swap(tab, fw + 1);
+    const Real *Fbw = Tab<Real>::swap(tab, bw), *Gbw = Tab<Real>::swap(tab, bw + 1);
+    const Real *Z = Tab<Real>::z(tab, OP);  // ZM2M = 0, ZM2L = 1, ZL2L = 2 match OP
+    const int TP = tab.P;
+    const Real *rr = reinterpret_cast<const Real *>(a.r);
+    const bool acc = (a.flags & 1u) != 0;
+
+    for (int64_t t = blockIdx.x; t < a.count; t += gridDim.x) {
+        const int64_t si = a.src ? a.src[t] : t;
+        const int64_t di = a.dst ? a.dst[t] : t;
+        const Real *in = reinterpret_cast<const Real *>(a.in) + si * a.ld_in;
+        Real *out = reinterpret_cast<Real *>(a.out) + di * a.ld_out;
+        const Geometry g = shift_geometry((double)rr[3 * t], (double)rr[3 * t + 1], (double)rr[3 * t + 2]);
+
+        if (g.valid != 1) {
+            // M2M / L2L with r = 0: identity (truncated / zero-padded); otherwise NaN + flag
+            const bool ident = (g.valid == 0) && (OP != OP_M2L);
+            const int rows_copy = ident ? (p_in < p_out ? p_in : p_out) : 0;
+            for (int i = lane; i < p_out * (p_out + 1); i += 64) {
+                const int nn = solid_row(i);
+                const bool im0 = (i == nn * (nn + 1) + 1);
+                Real v;
+                if (!ident)
+                    v = (Real)NAN;
+                else
+                    v = (nn < rows_copy && !im0) ? in[i] : (Real)0;
+                out[i] = (acc && ident) ? out[i] + v : v;
+            }
+            if (!ident && lane == 0) raise_device_error(a.err, -3);
+            continue;
+        }
+
+        // ---- step 1: powers (FP64, rounded once to Real) ----
+        if (lane == 0) {
+            double cr = 1.0, ci = 0.0, dr = 1.0, dI = 0.0;
+            for (int j = 0; j < Pm; ++j) {
+                ear[j] = (Real)cr;
+                eai[j] = (Real)ci;
+                ebr[j] = (Real)dr;
+                ebi[j] = (Real)dI;
+                double t1 = cr * g.ca - ci * g.sa;
+                ci = cr * g.sa + ci * g.ca;
+                cr = t1;
+                t1 = dr * g.cb - dI * g.sb;
+                dI = dr * g.sb + dI * g.cb;
+                dr = t1;
+            }
+            // s^j and |r|^j
+            double sp = 1.0, rp = 1.0;
+            for (int n = 0; n < Pm; ++n) {
+                // scale in:  M2L/M2M  M_n -> M_n / |r|^{n+1};  L2L  L_n -> L_n |r|^n
+                // scale out: M2L/L2L  L_n -> L_n / |r|^n;      M2M  M_n -> M_n |r|^{n+1}
+                if (OP == OP_L2L) {
+                    sc_in[n] = (Real)rp;
+                    sc_out[n] = (Real)sp;
+                } else if (OP == OP_M2L) {
+                    sc_in[n] = (Real)(sp * g.s);
+                    sc_out[n] = (Real)sp;
+                } else {
+                    sc_in[n] = (Real)(sp * g.s);
+                    sc_out[n] = (Real)(rp * g.R);
+                }
+                sp *= g.s;
+                rp *= g.R;
+            }
+        }
+        // ---- load input rows [0, p_in) ----
+        for (int i = lane; i < p_in * (p_in + 1); i += 64) A[i] = in[i];
+        __syncthreads();
+        // ---- step 2: scale + rotate a (Im C_n^0 of the input is ignored) ----
+        {
+            const int tri = p_in * (p_in + 1) / 2;
+            for (int c = lane; c < tri; c += 64) {
+                const int n = tri_row(c);
+                const int m = c - n * (n + 1) / 2;
+                const Real f = sc_in[n];
+                const Real x = A[solid_pos(n, m)] * f;
+                const Real y = (m == 0) ? (Real)0 : A[solid_pos(n, m) + 1] * f;
+                A[solid_pos(n, m)] = x * ear[m] - y * eai[m];
+                A[solid_pos(n, m) + 1] = x * eai[m] + y * ear[m];
+            }
+        }
+        __syncthreads();
+        swap_rows<Real>(Ffw, Gfw, A, B, p_in, lane);
+        __syncthreads();
+        zrot_rows<Real>(B, ebr, ebi, (Real)1, p_in, lane);
+        __syncthreads();
+        swap_rows<Real>(Ffw, Gfw, B, A, p_in, lane);
+        __syncthreads();
+        // ---- step 3: z-axis step, columns m, unit shift ----
+        {
+            const int tri = p_out * (p_out + 1) / 2;
+            for (int c = lane; c < tri; c += 64) {
+                const int o = tri_row(c);
+                const int m = c - o * (o + 1) / 2;
+                Real yr = 0, yi = 0;
+                if (m < p_in) {
+                    int lo = m, hi = p_in - 1;
+                    if (OP == OP_M2M) hi = (o < hi) ? o : hi;
+                    if (OP == OP_L2L) lo = o;
+                    const Real *zrow = Z + z_col_off(TP, m) + (int64_t)(o - m) * (TP - m) - m;
+                    for (int i = lo; i <= hi; ++i) {
+                        yr += zrow[i] * A[solid_pos(i, m)];
+                        yi += zrow[i] * A[solid_pos(i, m) + 1];
+                    }
+                }
+                B[solid_pos(o, m)] = yr;
+                B[solid_pos(o, m) + 1] = yi;
+            }
+        }
+        __syncthreads();
+        // ---- step 4: back rotation of the output rows ----
+        swap_rows<Real>(Fbw, Gbw, B, A, p_out, lane);
+        __syncthreads();
+        zrot_rows<Real>(A, ebr, ebi, (Real)-1, p_out, lane);
+        __syncthreads();
+        swap_rows<Real>(Fbw, Gbw, A, B, p_out, lane);
+        __syncthreads();
+        {
+            const int tri = p_out * (p_out + 1) / 2;
+            for (int c = lane; c < tri; c += 64) {
+                const int n = tri_row(c);
+                const int m = c - n * (n + 1) / 2;
+                const Real f = sc_out[n];
+                const Real x = B[solid_pos(n, m)] * f;
+                const Real y = B[solid_pos(n, m) + 1] * f;
+                // multiply by e^{-im a}
+                Real vr = x * ear[m] + y * eai[m];
+                Real vi = (m == 0) ? (Real)0 : (y * ear[m] - x * eai[m]);
+                if (acc) {
+                    vr += out[solid_pos(n, m)];
+                    if (m) vi += out[solid_pos(n, m) + 1];
+                }
+                out[solid_pos(n, m)] = vr;
+                out[solid_pos(n, m) + 1] = vi;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_general(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s)
+{
+    if (a.count <= 0) return hipSuccess;
+    const int Pm = a.p_in > a.p_out ? a.p_in : a.p_out;
+    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const size_t smem = (size_t)(2 * Pm * (Pm + 1) + 6 * Pm) * elem;
+    const int64_t grid64 = a.count < (1 << 20) ? a.count : (1 << 20);
+    const dim3 grid((unsigned)grid64), block(64);
+#define SH_LAUNCH(T, OPV) hipLaunchKernelGGL((k_general<T, OPV>), grid, block, smem, s, tab, a)
+    if (f32) {
+        if (a.op == OP_M2M) SH_LAUNCH(float, OP_M2M);
+        else if (a.op == OP_M2L) SH_LAUNCH(float, OP_M2L);
+        else SH_LAUNCH(float, OP_L2L);
+    } else {
+        if (a.op == OP_M2M) SH_LAUNCH(double, OP_M2M);
+        else if (a.op == OP_M2L) SH_LAUNCH(double, OP_M2L);
+        else SH_LAUNCH(double, OP_L2L);
+    }
+#undef SH_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace shfmm
