@@ -89,13 +89,16 @@ def cpu_baseline(seconds_target=10.0):
     t0 = time.perf_counter()
     o.translate_batch("m2l", P, P, r[:512], M[:512], nthreads=threads)
     dt = time.perf_counter() - t0
-    n = int(min(1 << 20, max(1024, 512 * seconds_target / max(dt, 1e-6))))
-    reps = (n + len(M) - 1) // len(M)
-    Mr = np.tile(M, (reps, 1))[:n]
-    rr = np.tile(r, (reps, 1))[:n]
+    # one pass over a 2^16-translation sample takes ~dt * 128; repeat it to ~seconds_target
+    reps = (1 << 16) // len(M)
+    Mr = np.tile(M, (reps, 1))
+    rr = np.tile(r, (reps, 1))
+    passes = int(max(1, min(64, seconds_target / max(dt * 128, 1e-6))))
     t0 = time.perf_counter()
-    o.translate_batch("m2l", P, P, rr, Mr, nthreads=threads)
+    for _ in range(passes):
+        o.translate_batch("m2l", P, P, rr, Mr, nthreads=threads)
     dt = time.perf_counter() - t0
+    n = passes * len(Mr)
     cpu = ""
     try:
         for line in open("/proc/cpuinfo"):

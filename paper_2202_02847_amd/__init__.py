@@ -64,6 +64,13 @@ def lib():
     """The loaded ctypes library (raises LibraryMissing if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname (libamdhip64.so.7); loading
+        # torch first makes this library bind to that runtime, so that torch's device
+        # memory, streams, events and synchronisation are the ones the kernels use.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - C-only environments
+            pass
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(f"{LIB_PATH} not built: run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)

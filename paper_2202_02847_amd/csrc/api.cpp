@@ -172,10 +172,11 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SH_EDEVICE;
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SH_EDEVICE;
         shfmm::HostTables ht;
-        shfmm::build_tables(max_order, ht);
+        shfmm::build_tables(shfmm::kMaxOrder, ht);
         DeviceGuard g(device);
         if (!g.ok) return SH_EDEVICE;
-        // layout: swap64[4] | z64[3] | swap32[4] | z32[3] | err flag, each 256-byte aligned
+        // layout: swap64[4] | z64[3] | swap32[4] | z32[3] | swap64n[4] | z64n[3] | err flag,
+        // each 256-byte aligned
         auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
         size_t total = 0;
         std::vector<size_t> offs;
@@ -183,6 +184,8 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z64[k].size() * 8); }
         for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.swap32[k].size() * 4); }
         for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z32[k].size() * 4); }
+        for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.swap64n[k].size() * 8); }
+        for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z64n[k].size() * 8); }
         offs.push_back(total);
         total += 256;
         void *mem = nullptr;
@@ -211,10 +214,18 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
             ok &= hipMemcpy(base + offs[idx], ht.z32[k].data(), ht.z32[k].size() * 4, hipMemcpyHostToDevice) == hipSuccess;
             c->tabs.z32[k] = reinterpret_cast<const float *>(base + offs[idx]);
         }
+        for (int k = 0; k < 4; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.swap64n[k].data(), ht.swap64n[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.swap64n[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 3; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.z64n[k].data(), ht.z64n[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.z64n[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
         c->err_flag = reinterpret_cast<int *>(base + offs[idx]);
         ok &= hipMemset(c->err_flag, 0, sizeof(int)) == hipSuccess;
         ok &= hipDeviceSynchronize() == hipSuccess;
-        c->tabs.P = max_order;
+        c->tabs.P = shfmm::kMaxOrder;
         c->device = device;
         c->max_order = max_order;
         c->dev_mem = mem;

@@ -10,26 +10,41 @@ namespace shfmm {
 // Swap matrices: dense (n+1)x(n+1) row-major per degree n at offset n(n+1)(2n+1)/6,
 // kinds F, G (M side), FL, GL (L side).  z coefficients: column m block at
 // sum_{j<m} (P-j)^2, entry [out-m][in-m] with row length P-m, P = table order.
+// Three table sets: paper basis in FP64 (FP64 path), normalised basis in FP32 (FP32 path)
+// and normalised basis in FP64 (FP32 path with FP64 arithmetic at high order).
 struct DevTables {
     const double *swap64[4];
     const float *swap32[4];
+    const double *swap64n[4];
     const double *z64[3];
     const float *z32[3];
+    const double *z64n[3];
     int P;
 };
 
-template <typename Real>
+// Table set for I/O type Real and arithmetic type Acc: Real = double uses the paper basis,
+// Real = float uses the normalised basis in the arithmetic type.
+template <typename Real, typename Acc>
 struct Tab;
 template <>
-struct Tab<double> {
+struct Tab<double, double> {
     __device__ static const double *swap(const DevTables &t, int k) { return t.swap64[k]; }
     __device__ static const double *z(const DevTables &t, int k) { return t.z64[k]; }
 };
 template <>
-struct Tab<float> {
+struct Tab<float, float> {
     __device__ static const float *swap(const DevTables &t, int k) { return t.swap32[k]; }
     __device__ static const float *z(const DevTables &t, int k) { return t.z32[k]; }
 };
+template <>
+struct Tab<float, double> {
+    __device__ static const double *swap(const DevTables &t, int k) { return t.swap64n[k]; }
+    __device__ static const double *z(const DevTables &t, int k) { return t.z64n[k]; }
+};
+
+// The FP32 path switches its arithmetic to FP64 from this order on (gfx950 runs
+// non-packed FP32 and FP64 FMA at the same rate; HBM traffic stays FP32).
+constexpr int kF32WideOrder = 20;
 
 enum { OP_M2M = 0, OP_M2L = 1, OP_L2L = 2 };
 enum { SW_F = 0, SW_G = 1, SW_FL = 2, SW_GL = 3 };

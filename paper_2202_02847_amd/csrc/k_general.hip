@@ -67,28 +67,30 @@ __device__ __forceinline__ void zrot_rows(Real *x, const Real *er, const Real *e
     }
 }
 
-template <typename Real, int OP>
+// Real: type of the solids and shifts in memory; Acc: arithmetic type (LDS state, tables).
+template <typename Real, typename Acc, int OP>
 __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     const int p_in = a.p_in, p_out = a.p_out;
     const int Pm = p_in > p_out ? p_in : p_out;
     const int S = Pm * (Pm + 1);
-    Real *A = reinterpret_cast<Real *>(smem_raw);
-    Real *B = A + S;
-    Real *ear = B + S;
-    Real *eai = ear + Pm;
-    Real *ebr = eai + Pm;
-    Real *ebi = ebr + Pm;
-    Real *sc_in = ebi + Pm;
-    Real *sc_out = sc_in + Pm;
+    Acc *A = reinterpret_cast<Acc *>(smem_raw);
+    Acc *B = A + S;
+    Acc *ear = B + S;
+    Acc *eai = ear + Pm;
+    Acc *ebr = eai + Pm;
+    Acc *ebi = ebr + Pm;
+    Acc *sc_in = ebi + Pm;
+    Acc *sc_out = sc_in + Pm;
     const int lane = threadIdx.x;
 
     const int fw = (OP == OP_L2L) ? SW_FL : SW_F;
     const int bw = (OP == OP_M2M) ? SW_F : SW_FL;
-    const Real *Ffw = Tab<Real>::swap(tab, fw), *Gfw = Tab<Real>::swap(tab, fw + 1);
-    const Real *Fbw = Tab<Real>::swap(tab, bw), *Gbw = Tab<Real>::swap(tab, bw + 1);
-    const Real *Z = Tab<Real>::z(tab, OP);  // ZM2M = 0, ZM2L = 1, ZL2L = 2 match OP
+    using T = Tab<Real, Acc>;
+    const Acc *Ffw = T::swap(tab, fw), *Gfw = T::swap(tab, fw + 1);
+    const Acc *Fbw = T::swap(tab, bw), *Gbw = T::swap(tab, bw + 1);
+    const Acc *Z = T::z(tab, OP);  // ZM2M = 0, ZM2L = 1, ZL2L = 2 match OP
     const int TP = tab.P;
     const Real *rr = reinterpret_cast<const Real *>(a.r);
     const bool acc = (a.flags & 1u) != 0;
@@ -122,10 +124,10 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
         if (lane == 0) {
             double cr = 1.0, ci = 0.0, dr = 1.0, dI = 0.0;
             for (int j = 0; j < Pm; ++j) {
-                ear[j] = (Real)cr;
-                eai[j] = (Real)ci;
-                ebr[j] = (Real)dr;
-                ebi[j] = (Real)dI;
+                ear[j] = (Acc)cr;
+                eai[j] = (Acc)ci;
+                ebr[j] = (Acc)dr;
+                ebi[j] = (Acc)dI;
                 double t1 = cr * g.ca - ci * g.sa;
                 ci = cr * g.sa + ci * g.ca;
                 cr = t1;
@@ -139,21 +141,21 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
                 // scale in:  M2L/M2M  M_n -> M_n / |r|^{n+1};  L2L  L_n -> L_n |r|^n
                 // scale out: M2L/L2L  L_n -> L_n / |r|^n;      M2M  M_n -> M_n |r|^{n+1}
                 if (OP == OP_L2L) {
-                    sc_in[n] = (Real)rp;
-                    sc_out[n] = (Real)sp;
+                    sc_in[n] = (Acc)rp;
+                    sc_out[n] = (Acc)sp;
                 } else if (OP == OP_M2L) {
-                    sc_in[n] = (Real)(sp * g.s);
-                    sc_out[n] = (Real)sp;
+                    sc_in[n] = (Acc)(sp * g.s);
+                    sc_out[n] = (Acc)sp;
                 } else {
-                    sc_in[n] = (Real)(sp * g.s);
-                    sc_out[n] = (Real)(rp * g.R);
+                    sc_in[n] = (Acc)(sp * g.s);
+                    sc_out[n] = (Acc)(rp * g.R);
                 }
                 sp *= g.s;
                 rp *= g.R;
             }
         }
         // ---- load input rows [0, p_in) ----
-        for (int i = lane; i < p_in * (p_in + 1); i += 64) A[i] = in[i];
+        for (int i = lane; i < p_in * (p_in + 1); i += 64) A[i] = (Acc)in[i];
         __syncthreads();
         // ---- step 2: scale + rotate a (Im C_n^0 of the input is ignored) ----
         {
@@ -161,19 +163,19 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
             for (int c = lane; c < tri; c += 64) {
                 const int n = tri_row(c);
                 const int m = c - n * (n + 1) / 2;
-                const Real f = sc_in[n];
-                const Real x = A[solid_pos(n, m)] * f;
-                const Real y = (m == 0) ? (Real)0 : A[solid_pos(n, m) + 1] * f;
+                const Acc f = sc_in[n];
+                const Acc x = A[solid_pos(n, m)] * f;
+                const Acc y = (m == 0) ? (Acc)0 : A[solid_pos(n, m) + 1] * f;
                 A[solid_pos(n, m)] = x * ear[m] - y * eai[m];
                 A[solid_pos(n, m) + 1] = x * eai[m] + y * ear[m];
             }
         }
         __syncthreads();
-        swap_rows<Real>(Ffw, Gfw, A, B, p_in, lane);
+        swap_rows<Acc>(Ffw, Gfw, A, B, p_in, lane);
         __syncthreads();
-        zrot_rows<Real>(B, ebr, ebi, (Real)1, p_in, lane);
+        zrot_rows<Acc>(B, ebr, ebi, (Acc)1, p_in, lane);
         __syncthreads();
-        swap_rows<Real>(Ffw, Gfw, B, A, p_in, lane);
+        swap_rows<Acc>(Ffw, Gfw, B, A, p_in, lane);
         __syncthreads();
         // ---- step 3: z-axis step, columns m, unit shift ----
         {
@@ -181,12 +183,12 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
             for (int c = lane; c < tri; c += 64) {
                 const int o = tri_row(c);
                 const int m = c - o * (o + 1) / 2;
-                Real yr = 0, yi = 0;
+                Acc yr = 0, yi = 0;
                 if (m < p_in) {
                     int lo = m, hi = p_in - 1;
                     if (OP == OP_M2M) hi = (o < hi) ? o : hi;
                     if (OP == OP_L2L) lo = o;
-                    const Real *zrow = Z + z_col_off(TP, m) + (int64_t)(o - m) * (TP - m) - m;
+                    const Acc *zrow = Z + z_col_off(TP, m) + (int64_t)(o - m) * (TP - m) - m;
                     for (int i = lo; i <= hi; ++i) {
                         yr += zrow[i] * A[solid_pos(i, m)];
                         yi += zrow[i] * A[solid_pos(i, m) + 1];
@@ -198,29 +200,29 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
         }
         __syncthreads();
         // ---- step 4: back rotation of the output rows ----
-        swap_rows<Real>(Fbw, Gbw, B, A, p_out, lane);
+        swap_rows<Acc>(Fbw, Gbw, B, A, p_out, lane);
         __syncthreads();
-        zrot_rows<Real>(A, ebr, ebi, (Real)-1, p_out, lane);
+        zrot_rows<Acc>(A, ebr, ebi, (Acc)-1, p_out, lane);
         __syncthreads();
-        swap_rows<Real>(Fbw, Gbw, A, B, p_out, lane);
+        swap_rows<Acc>(Fbw, Gbw, A, B, p_out, lane);
         __syncthreads();
         {
             const int tri = p_out * (p_out + 1) / 2;
             for (int c = lane; c < tri; c += 64) {
                 const int n = tri_row(c);
                 const int m = c - n * (n + 1) / 2;
-                const Real f = sc_out[n];
-                const Real x = B[solid_pos(n, m)] * f;
-                const Real y = B[solid_pos(n, m) + 1] * f;
+                const Acc f = sc_out[n];
+                const Acc x = B[solid_pos(n, m)] * f;
+                const Acc y = B[solid_pos(n, m) + 1] * f;
                 // multiply by e^{-im a}
-                Real vr = x * ear[m] + y * eai[m];
-                Real vi = (m == 0) ? (Real)0 : (y * ear[m] - x * eai[m]);
+                Acc vr = x * ear[m] + y * eai[m];
+                Acc vi = (m == 0) ? (Acc)0 : (y * ear[m] - x * eai[m]);
                 if (acc) {
-                    vr += out[solid_pos(n, m)];
-                    if (m) vi += out[solid_pos(n, m) + 1];
+                    vr += (Acc)out[solid_pos(n, m)];
+                    if (m) vi += (Acc)out[solid_pos(n, m) + 1];
                 }
-                out[solid_pos(n, m)] = vr;
-                out[solid_pos(n, m) + 1] = vi;
+                out[solid_pos(n, m)] = (Real)vr;
+                out[solid_pos(n, m) + 1] = (Real)vi;
             }
         }
         __syncthreads();
@@ -233,19 +235,24 @@ hipError_t launch_general(const DevTables &tab, const TransArgs &a, bool f32, hi
 {
     if (a.count <= 0) return hipSuccess;
     const int Pm = a.p_in > a.p_out ? a.p_in : a.p_out;
-    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const bool wide = f32 && Pm >= kF32WideOrder;  // FP32 I/O, FP64 arithmetic
+    const size_t elem = (f32 && !wide) ? sizeof(float) : sizeof(double);
     const size_t smem = (size_t)(2 * Pm * (Pm + 1) + 6 * Pm) * elem;
     const int64_t grid64 = a.count < (1 << 20) ? a.count : (1 << 20);
     const dim3 grid((unsigned)grid64), block(64);
-#define SH_LAUNCH(T, OPV) hipLaunchKernelGGL((k_general<T, OPV>), grid, block, smem, s, tab, a)
-    if (f32) {
-        if (a.op == OP_M2M) SH_LAUNCH(float, OP_M2M);
-        else if (a.op == OP_M2L) SH_LAUNCH(float, OP_M2L);
-        else SH_LAUNCH(float, OP_L2L);
+#define SH_LAUNCH(T, A, OPV) hipLaunchKernelGGL((k_general<T, A, OPV>), grid, block, smem, s, tab, a)
+    if (wide) {
+        if (a.op == OP_M2M) SH_LAUNCH(float, double, OP_M2M);
+        else if (a.op == OP_M2L) SH_LAUNCH(float, double, OP_M2L);
+        else SH_LAUNCH(float, double, OP_L2L);
+    } else if (f32) {
+        if (a.op == OP_M2M) SH_LAUNCH(float, float, OP_M2M);
+        else if (a.op == OP_M2L) SH_LAUNCH(float, float, OP_M2L);
+        else SH_LAUNCH(float, float, OP_L2L);
     } else {
-        if (a.op == OP_M2M) SH_LAUNCH(double, OP_M2M);
-        else if (a.op == OP_M2L) SH_LAUNCH(double, OP_M2L);
-        else SH_LAUNCH(double, OP_L2L);
+        if (a.op == OP_M2M) SH_LAUNCH(double, double, OP_M2M);
+        else if (a.op == OP_M2L) SH_LAUNCH(double, double, OP_M2L);
+        else SH_LAUNCH(double, double, OP_L2L);
     }
 #undef SH_LAUNCH
     return hipGetLastError();

@@ -78,12 +78,17 @@ i128 folded(int n, SwapKind kind, int m, int l)
     return 0;
 }
 
-// x! as long double
+// x! as long double (x <= 2 kMaxOrder), from a table filled once
 long double fact_ld(int x)
 {
-    long double f = 1;
-    for (int j = 2; j <= x; ++j) f *= j;
-    return f;
+    static const std::vector<long double> tab = [] {
+        std::vector<long double> t(2 * kMaxOrder + 1);
+        t[0] = 1;
+        for (int j = 1; j <= 2 * kMaxOrder; ++j) t[j] = t[j - 1] * j;
+        return t;
+    }();
+    if (x < 0 || x > 2 * kMaxOrder) throw std::out_of_range("factorial");
+    return tab[x];
 }
 
 // w_n^m / w_n^l = sqrt((n+m)!(n-m)! / ((n+l)!(n-l)!)) in long double

@@ -52,8 +52,10 @@ void swap_matrix_ld(int n, SwapKind kind, bool normalised, long double *out);
 // Raw-basis entry (m, l) of degree n, correctly rounded to double from the exact value.
 double swap_entry_f64(int n, SwapKind kind, int m, int l);
 
+// Tables are always built for kMaxOrder: the layout (block offsets) then depends on
+// compile-time constants only, and kernels can address entries with fixed offsets.
 struct HostTables {
-    int P = 0;                           // max order covered
+    int P = 0;                           // order the layout is built for (kMaxOrder)
     std::vector<double> swap64[4];       // raw basis, FP64
     std::vector<float> swap32[4];        // normalised basis, FP32
     std::vector<double> swap64n[4];      // normalised basis, FP64 (used by the MFMA forms)
@@ -62,7 +64,7 @@ struct HostTables {
     std::vector<double> z64n[3];         // normalised basis z coefficients, FP64
 };
 
-// Builds every table for orders up to P (1 <= P <= kMaxOrder).
+// Builds every table for orders up to P (1 <= P <= kMaxOrder); sh_create uses kMaxOrder.
 void build_tables(int P, HostTables &t);
 
 // Single z coefficient (long double) -- used by build_tables and the host tests.

@@ -55,13 +55,32 @@ def _inputs(orc, op, p_in, count, seed, lengths):
     return r, C
 
 
-def _check(got, ref, p_out, kind, tol, what):
+# Conditioning: for some inputs (high order, shift shorter than the cluster radius) the
+# plain FP64 sums themselves lose digits -- the FP64 oracle then differs from the exact
+# value by more than 1e-12.  FP64 results are therefore compared with the long-double
+# oracle, against max(1e-12, COND_FACTOR x the FP64 oracle's own error): 1e-12 wherever
+# the definition is that well conditioned in FP64, otherwise no worse than a small
+# multiple of the plain FP64 definition.
+COND_FACTOR = 16.0
+
+
+def _check(got, ref, p_out, kind, tol, what, ref_ld=None):
     worst = 0.0
     for i in range(ref.shape[0]):
-        e = max_degree_error(got[i], ref[i], p_out, kind)
+        if ref_ld is not None:
+            own = max_degree_error(ref[i], ref_ld[i], p_out, kind)
+            bound = max(tol, COND_FACTOR * own)
+            e = max_degree_error(got[i], ref_ld[i], p_out, kind)
+        else:
+            bound = tol
+            e = max_degree_error(got[i], ref[i], p_out, kind)
         worst = max(worst, e)
-        assert e <= tol, f"{what} translation {i}: {e:.3e} > {tol:.1e}"
+        assert e <= bound, f"{what} translation {i}: {e:.3e} > {bound:.1e}"
     return worst
+
+
+def _ld_ref(op, p_in, p_out, r, C):
+    return oracle.get("longdouble").translate_batch(op, p_in, p_out, r, C, nthreads=8).astype(np.float64)
 
 
 LENGTHS = {"m2l": (2.0, 4.0), "m2m": (0.25, 0.5), "l2l": (0.25, 0.5)}
@@ -81,8 +100,8 @@ def test_orders(ctx, orc, op, dtype, p_in, p_out):
     r, C = _inputs(orc, op, p_in, count, 1000 + 37 * p_in + p_out, LENGTHS[op])
     ref = orc.translate_batch(op, p_in, p_out, r, C)
     got, _ = run_batch(ctx, op, dtype, p_in, p_out, r, C)
-    tol = TOL[dtype]
-    _check(got, ref, p_out, OUT_KIND[op], tol, f"{op} {DT_ID[dtype]} {p_in}->{p_out}")
+    ref_ld = _ld_ref(op, p_in, p_out, r, C) if dtype == sh.SH_F64 else None
+    _check(got, ref, p_out, OUT_KIND[op], TOL[dtype], f"{op} {DT_ID[dtype]} {p_in}->{p_out}", ref_ld)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DT_ID.get)
@@ -118,7 +137,8 @@ def test_octree_full_size_sampled(ctx, orc, P):
     idx = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.integers(0, n, 250)]))
     got = d_L[torch.from_numpy(idx).to(dev)].cpu().numpy()
     ref = orc.translate_batch("m2l", P, P, c["r_m2l"][idx], M[idx], nthreads=8)
-    _check(got, ref, P, "L", TOL[sh.SH_F64], f"octree P={P}")
+    ref_ld = _ld_ref("m2l", P, P, c["r_m2l"][idx], M[idx])
+    _check(got, ref, P, "L", TOL[sh.SH_F64], f"octree P={P}", ref_ld)
     assert ctx.device_error() == 0
 
 
