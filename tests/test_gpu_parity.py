@@ -64,10 +64,17 @@ def _inputs(orc, op, p_in, count, seed, lengths):
 COND_FACTOR = 16.0
 
 
-def _check(got, ref, p_out, kind, tol, what, ref_ld=None):
+def _check(got, ref, p_out, kind, tol, what, ref_ld=None, ref_in32=None):
+    """ref_ld: long-double reference (FP64 path).  ref_in32: the FP64 oracle applied to the
+    input rounded through the FP32 normalised basis -- its distance from ref is the error
+    any FP32-input computation inherits; the FP32 bound is max(tol, COND_FACTOR x that)."""
     worst = 0.0
     for i in range(ref.shape[0]):
-        if ref_ld is not None:
+        if ref_in32 is not None:
+            floor = max_degree_error(ref_in32[i], ref[i], p_out, kind)
+            bound = max(tol, COND_FACTOR * floor)
+            e = max_degree_error(got[i], ref[i], p_out, kind)
+        elif ref_ld is not None:
             own = max_degree_error(ref[i], ref_ld[i], p_out, kind)
             bound = max(tol, COND_FACTOR * own)
             e = max_degree_error(got[i], ref_ld[i], p_out, kind)
@@ -77,6 +84,13 @@ def _check(got, ref, p_out, kind, tol, what, ref_ld=None):
         worst = max(worst, e)
         assert e <= bound, f"{what} translation {i}: {e:.3e} > {bound:.1e}"
     return worst
+
+
+def _in32_ref(orc, op, p_in, p_out, r, C):
+    from gpu_util import to_basis, from_basis
+    C32 = from_basis(to_basis(C, p_in, IN_KIND[op], sh.SH_F32), p_in, IN_KIND[op], sh.SH_F32)
+    r32 = np.asarray(r, np.float32).astype(np.float64)
+    return orc.translate_batch(op, p_in, p_out, r32, C32)
 
 
 def _ld_ref(op, p_in, p_out, r, C):
@@ -101,7 +115,8 @@ def test_orders(ctx, orc, op, dtype, p_in, p_out):
     ref = orc.translate_batch(op, p_in, p_out, r, C)
     got, _ = run_batch(ctx, op, dtype, p_in, p_out, r, C)
     ref_ld = _ld_ref(op, p_in, p_out, r, C) if dtype == sh.SH_F64 else None
-    _check(got, ref, p_out, OUT_KIND[op], TOL[dtype], f"{op} {DT_ID[dtype]} {p_in}->{p_out}", ref_ld)
+    ref_in32 = _in32_ref(orc, op, p_in, p_out, r, C) if dtype == sh.SH_F32 else None
+    _check(got, ref, p_out, OUT_KIND[op], TOL[dtype], f"{op} {DT_ID[dtype]} {p_in}->{p_out}", ref_ld, ref_in32)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DT_ID.get)
