@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -80,7 +81,12 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
     const bool f32 = dtype == SH_F32;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
-    if (shfmm::lpt_available(op, f32, p_in, p_out))
+    // the fixed-order kernels move (Re, Im) pairs with vector accesses
+    const size_t pair = f32 ? 2 * sizeof(float) : 2 * sizeof(double);
+    const bool pair_aligned = (reinterpret_cast<uintptr_t>(in) % pair) == 0 &&
+                              (reinterpret_cast<uintptr_t>(out) % pair) == 0 && ld_in % 2 == 0 &&
+                              ld_out % 2 == 0;
+    if (pair_aligned && shfmm::lpt_available(op, f32, p_in, p_out))
         e = shfmm::launch_lpt(ctx->tabs, a, f32, s);
     else
         e = shfmm::launch_general(ctx->tabs, a, f32, s);

@@ -47,6 +47,10 @@ struct Tab<float, double> {
 constexpr int kF32WideOrder = 20;
 
 enum { OP_M2M = 0, OP_M2L = 1, OP_L2L = 2 };
+
+// Order the device tables are laid out for (every context builds them up to this order),
+// so that kernels with compile-time orders address table entries at fixed offsets.
+constexpr int kZTableOrder = 64;
 enum { SW_F = 0, SW_G = 1, SW_FL = 2, SW_GL = 3 };
 
 __host__ __device__ constexpr int swap_off(int n) { return n * (n + 1) * (2 * n + 1) / 6; }

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
                     v = (Real)NAN;
                 else
                     v = (nn < rows_copy && !im0) ? in[i] : (Real)0;
-                out[i] = (acc && ident) ? out[i] + v : v;
+                out[i] = im0 ? (Real)0 : ((acc && ident) ? out[i] + v : v);
             }
             if (!ident && lane == 0) raise_device_error(a.err, -3);
             continue;
