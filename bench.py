@@ -112,6 +112,23 @@ def cpu_baseline(seconds_target=10.0):
                       f"double-height O(P^4) sum, OpenMP over {threads} threads, {dt:.1f} s; {cpu}"}
 
 
+def run_counters(sh, ctx, torch, dev, P, steps):
+    """A short program for hardware-counter runs: a plain copy of 2^27 doubles (1 GiB read,
+    1 GiB written) and `steps` octree M2L launches at order P."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    n = 1 << 20 if P <= 16 else 1 << 18
+    I = make_octree_inputs(sh, ctx, torch, dev, P, n)
+    d_out = torch.empty((n, solid(P)), dtype=torch.float64, device=dev)
+    for _ in range(max(1, steps)):
+        sh.sh_m2l_batch_f64(ctx, P, P, n, I["r"], I["M"], solid(P), d_out, solid(P))
+    torch.cuda.synchronize()
+    log(f"[counters] done: copy 1 GiB + {max(1, steps)} x M2L P={P} n={n}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +137,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip P=16/30, FP32 and naive extras")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--counters", type=int, default=0, metavar="P",
+                    help="counter-collection mode: one 1 GiB copy (the reference kernel for "
+                         "FETCH_SIZE/WRITE_SIZE scaling), then --steps launches of the octree M2L "
+                         "at order P (FP64), nothing else; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -131,6 +152,9 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = sh.Context(max_order=32, device=0)
+    if args.counters:
+        run_counters(sh, ctx, torch, dev, args.counters, args.steps)
+        return
     P, n, nc = 10, 1 << 20, 1 << 17
     log(f"[bench] generating octree inputs P={P} n={n}")
     I = make_octree_inputs(sh, ctx, torch, dev, P, n, n_child=nc)

@@ -85,7 +85,7 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
     const size_t pair = f32 ? 2 * sizeof(float) : 2 * sizeof(double);
     const bool pair_aligned = (reinterpret_cast<uintptr_t>(in) % pair) == 0 &&
                               (reinterpret_cast<uintptr_t>(out) % pair) == 0 && ld_in % 2 == 0 &&
-                              ld_out % 2 == 0;
+                              ld_out % 2 == 0 && ld_in < (1 << 24) && ld_out < (1 << 24);
     if (pair_aligned && shfmm::lpt_available(op, f32, p_in, p_out))
         e = shfmm::launch_lpt(ctx->tabs, a, f32, s);
     else
@@ -192,6 +192,9 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z32[k].size() * 4); }
         for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.swap64n[k].size() * 8); }
         for (int k = 0; k < 3; ++k) { offs.push_back(total); total += al(ht.z64n[k].size() * 8); }
+        for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk64[k].size() * 8); }
+        for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk32[k].size() * 4); }
+        for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk64n[k].size() * 8); }
         offs.push_back(total);
         total += 256;
         void *mem = nullptr;
@@ -227,6 +230,18 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         for (int k = 0; k < 3; ++k, ++idx) {
             ok &= hipMemcpy(base + offs[idx], ht.z64n[k].data(), ht.z64n[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
             c->tabs.z64n[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 2; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.pk64[k].data(), ht.pk64[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.pk64[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 2; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.pk32[k].data(), ht.pk32[k].size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.pk32[k] = reinterpret_cast<const float *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 2; ++k, ++idx) {
+            ok &= hipMemcpy(base + offs[idx], ht.pk64n[k].data(), ht.pk64n[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.pk64n[k] = reinterpret_cast<const double *>(base + offs[idx]);
         }
         c->err_flag = reinterpret_cast<int *>(base + offs[idx]);
         ok &= hipMemset(c->err_flag, 0, sizeof(int)) == hipSuccess;

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "layout.hpp"
+
 namespace shfmm {
 
 // Constant tables resident in device memory (built and uploaded once per context).
@@ -19,6 +21,9 @@ struct DevTables {
     const double *z64[3];
     const float *z32[3];
     const double *z64n[3];
+    const double *pk64[2];   // packed swap tables, [0] M side (F, G), [1] L side (FL, GL)
+    const float *pk32[2];
+    const double *pk64n[2];
     int P;
 };
 
@@ -30,16 +35,19 @@ template <>
 struct Tab<double, double> {
     __device__ static const double *swap(const DevTables &t, int k) { return t.swap64[k]; }
     __device__ static const double *z(const DevTables &t, int k) { return t.z64[k]; }
+    __device__ static const double *packed(const DevTables &t, int side) { return t.pk64[side]; }
 };
 template <>
 struct Tab<float, float> {
     __device__ static const float *swap(const DevTables &t, int k) { return t.swap32[k]; }
     __device__ static const float *z(const DevTables &t, int k) { return t.z32[k]; }
+    __device__ static const float *packed(const DevTables &t, int side) { return t.pk32[side]; }
 };
 template <>
 struct Tab<float, double> {
     __device__ static const double *swap(const DevTables &t, int k) { return t.swap64n[k]; }
     __device__ static const double *z(const DevTables &t, int k) { return t.z64n[k]; }
+    __device__ static const double *packed(const DevTables &t, int side) { return t.pk64n[side]; }
 };
 
 // The FP32 path switches its arithmetic to FP64 from this order on (gfx950 runs
@@ -53,13 +61,6 @@ enum { OP_M2M = 0, OP_M2L = 1, OP_L2L = 2 };
 constexpr int kZTableOrder = 64;
 enum { SW_F = 0, SW_G = 1, SW_FL = 2, SW_GL = 3 };
 
-__host__ __device__ constexpr int swap_off(int n) { return n * (n + 1) * (2 * n + 1) / 6; }
-__host__ __device__ constexpr int solid_pos(int n, int m) { return n * (n + 1) + 2 * m; }
-// start of column block m of a z-coefficient table of order P: sum_{j<m} (P-j)^2
-__host__ __device__ constexpr int64_t z_col_off(int P, int m)
-{
-    return ((int64_t)P * (P + 1) * (2 * P + 1) - (int64_t)(P - m) * (P - m + 1) * (2 * (P - m) + 1)) / 6;
-}
 
 // Geometry of a shift (Section 3.4, step 1): |r|, rho = sqrt(x^2+y^2) and the two
 // z-rotation angles, without trigonometric functions:

@@ -1,0 +1,8 @@
+// Fixed-order lane-per-translation kernels: double, L2L, orders 2..16.
+#include "lpt_impl.hpp"
+
+namespace shfmm {
+namespace lpt {
+template hipError_t launch_fixed<double, double, OP_L2L>(int, const DevTables &, const TransArgs &, hipStream_t);
+}  // namespace lpt
+}  // namespace shfmm

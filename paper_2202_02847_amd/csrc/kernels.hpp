@@ -27,6 +27,9 @@ struct TransArgs {
 // General rotation kernel: any orders up to the table order, one wavefront per translation.
 hipError_t launch_general(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s);
 
+// Highest order with a fixed-order (lane-per-translation) kernel.
+constexpr int kLptMaxOrder = 16;
+
 // Lane-per-translation rotation kernel for common equal orders; returns false when no
 // specialisation exists for (op, dtype, p_in, p_out) (the caller falls back).
 bool lpt_available(int op, bool f32, int p_in, int p_out);

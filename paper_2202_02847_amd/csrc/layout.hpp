@@ -1,0 +1,50 @@
+// Memory layouts shared by the host table builder and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace shfmm {
+
+// dense (n+1)x(n+1) swap block of degree n starts at n(n+1)(2n+1)/6
+__host__ __device__ constexpr int swap_off(int n) { return n * (n + 1) * (2 * n + 1) / 6; }
+// Re C_n^m of a solid
+__host__ __device__ constexpr int solid_pos(int n, int m) { return n * (n + 1) + 2 * m; }
+// start of column block m of a z-coefficient table of order P: sum_{j<m} (P-j)^2
+__host__ __device__ constexpr int64_t z_col_off(int P, int m)
+{
+    return ((int64_t)P * (P + 1) * (2 * P + 1) - (int64_t)(P - m) * (P - m + 1) * (2 * (P - m) + 1)) / 6;
+}
+
+// Packed swap tables (the paper's packing, Section 3.2, Fig. 3, for scalar loads): for each
+// degree n and output order m = 0..n, first the non-zero entries of the real-part matrix
+// (F or FL: l = 0..n with m + l + n even), then those of the imaginary-part matrix (G or
+// GL: m >= 1, l = 1..n with m + l + n odd), l ascending.  The kernels read them in exactly
+// this order, so consecutive entries are contiguous in memory.
+__host__ __device__ constexpr int packed_re_count(int n, int m)
+{
+    int c = 0;
+    for (int l = 0; l <= n; ++l) c += ((m + l + n) % 2 == 0);
+    return c;
+}
+__host__ __device__ constexpr int packed_im_count(int n, int m)
+{
+    int c = 0;
+    if (m == 0) return 0;
+    for (int l = 1; l <= n; ++l) c += ((m + l + n) % 2 == 1);
+    return c;
+}
+__host__ __device__ constexpr int packed_row_count(int n)
+{
+    int c = 0;
+    for (int m = 0; m <= n; ++m) c += packed_re_count(n, m) + packed_im_count(n, m);
+    return c;
+}
+__host__ __device__ constexpr int packed_off(int n)
+{
+    int c = 0;
+    for (int j = 0; j < n; ++j) c += packed_row_count(j);
+    return c;
+}
+
+}  // namespace shfmm

@@ -191,6 +191,27 @@ void build_tables(int P, HostTables &t)
             }
         }
     }
+    // packed non-zeros in the order the fixed-order kernels consume them
+    auto pack = [&](const auto &re, const auto &im, auto &out) {
+        out.assign(packed_off(P), 0);
+        int64_t at = 0;
+        for (int n = 0; n < P; ++n) {
+            const int64_t off = swap_offset(n);
+            for (int m = 0; m <= n; ++m) {
+                for (int l = 0; l <= n; ++l)
+                    if ((m + l + n) % 2 == 0) out[at++] = re[off + m * (n + 1) + l];
+                if (m > 0)
+                    for (int l = 1; l <= n; ++l)
+                        if ((m + l + n) % 2 == 1) out[at++] = im[off + m * (n + 1) + l];
+            }
+        }
+        if (at != packed_off(P)) throw std::logic_error("packed size");
+    };
+    for (int side = 0; side < 2; ++side) {
+        pack(t.swap64[2 * side], t.swap64[2 * side + 1], t.pk64[side]);
+        pack(t.swap32[2 * side], t.swap32[2 * side + 1], t.pk32[side]);
+        pack(t.swap64n[2 * side], t.swap64n[2 * side + 1], t.pk64n[side]);
+    }
     for (int k = 0; k < 3; ++k) {
         t.z64[k].assign(z_table_size(P), 0.0);
         t.z32[k].assign(z_table_size(P), 0.0f);

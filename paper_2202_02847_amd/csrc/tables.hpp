@@ -25,6 +25,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "layout.hpp"
+
 namespace shfmm {
 
 constexpr int kMaxOrder = 64;
@@ -33,7 +35,7 @@ enum SwapKind { kF = 0, kG = 1, kFL = 2, kGL = 3 };
 enum ZKind { kZM2M = 0, kZM2L = 1, kZL2L = 2 };
 
 // dense (n+1)x(n+1) row-major block of degree n starts at swap_offset(n)
-inline int64_t swap_offset(int n) { return (int64_t)n * (n + 1) * (2 * n + 1) / 6; }
+inline int64_t swap_offset(int n) { return swap_off(n); }
 inline int64_t swap_table_size(int P) { return swap_offset(P); }
 
 // z-coefficient block of column m: (P-m) x (P-m), [out - m][in - m], starts at zoff(P, m)
@@ -62,6 +64,10 @@ struct HostTables {
     std::vector<double> z64[3];          // raw basis z coefficients, FP64
     std::vector<float> z32[3];           // normalised basis z coefficients, FP32
     std::vector<double> z64n[3];         // normalised basis z coefficients, FP64
+    // packed non-zeros (layout.hpp): [0] M side from (F, G), [1] L side from (FL, GL)
+    std::vector<double> pk64[2];
+    std::vector<float> pk32[2];
+    std::vector<double> pk64n[2];
 };
 
 // Builds every table for orders up to P (1 <= P <= kMaxOrder); sh_create uses kMaxOrder.
