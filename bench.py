@@ -60,6 +60,24 @@ def make_octree_inputs(sh, ctx, torch, dev, P, n, npts=32, seed_config=2, n_chil
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_p10_f64_octree_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the M2L P=10 FP64 kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs, if they were taken on the current kernel sources (else None)."""
+    from paper_2202_02847_amd import profiling
+
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != profiling.kernel_source_hash():
+        return None
+    return round(rec["traffic_bytes"])
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -198,7 +216,7 @@ def main():
     bpt = bytes_per_translation(P, P, 8)
     achieved = bpt * n / m2l_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "M2L P=10 FP64", "bytes_per_translation": bpt, "launch_ms": round(m2l_s * 1e3, 4)}
     extra = {"m2l_p10_f64_per_s": n / m2l_s,
              "m2m_l2l_per_step_ms": round(ms_step - m2l_s * 1e3, 4),
