@@ -78,6 +78,57 @@ def measured_traffic():
     return round(rec["traffic_bytes"])
 
 
+def norm_weights(sh, torch, dev, P, kind):
+    """Normalisation factors of a solid of order P (kind 0: multipole, 1: local), taken from
+    the library's host helper applied to a solid of ones."""
+    w = sh.sh_normalise_f64(kind, P, np.ones((1, solid(P))))[0]
+    return torch.from_numpy(w).to(dev)
+
+
+def run_mixed(sh, ctx, torch, dev, dtype, n=500_000, reps=5):
+    """The mixed-order work list: n items (M2M/M2L/L2L, orders 3..30 skewed toward 6..12,
+    |r| in [2, 6]) through one autotuned plan, executed as one graph launch per pass.
+    Inputs are device P2M multipoles of 20-point clusters (used as the input of every
+    item, L2L included: the values do not change the work), normalised for FP32."""
+    from paper_2202_02847_amd import arena
+    from paper_2202_02847_amd import workloads as wl
+
+    c = wl.config4(n)
+    op, p_in, p_out = c["op"], c["p_in"], c["p_out"]
+    in_off, in_total = arena.packed_offsets(p_in, group_by_order=True)
+    out_off, out_total = arena.packed_offsets(p_out)
+    f32 = dtype == sh.SH_F32
+    tdt = torch.float32 if f32 else torch.float64
+    d_in = torch.empty(in_total, dtype=tdt, device=dev)
+    npts = c["pts"].shape[1]
+    for P, first, idx in arena.order_blocks(p_in, in_off):
+        k = len(idx)
+        d_pts = torch.from_numpy(np.ascontiguousarray(c["pts"][idx])).to(dev)
+        d_q = torch.from_numpy(np.ascontiguousarray(c["q"][idx])).to(dev)
+        d_c = torch.zeros((k, 3), dtype=torch.float64, device=dev)
+        M = torch.empty((k, solid(P)), dtype=torch.float64, device=dev)
+        sh.sh_p2m_batch_f64(ctx, P, k, d_c, npts, d_pts, d_q, M, solid(P))
+        if f32:
+            M = M * norm_weights(sh, torch, dev, P, 0)
+        d_in[first:first + M.numel()] = M.reshape(-1).to(tdt)
+    del c["pts"], c["q"]
+    items = sh.make_items(op, p_in, p_out, in_off, out_off, c["r"])
+    t0 = time.perf_counter()
+    plan = sh.Plan(ctx, dtype, items, sh.SH_PLAN_AUTOTUNE)
+    t_plan = time.perf_counter() - t0
+    d_out = torch.empty(out_total, dtype=tdt, device=dev)
+    t = time_launch(torch, lambda: plan.execute(d_in, in_total, d_out, out_total), reps)
+    assert bool(torch.isfinite(d_out).all()), "non-finite output in the mixed list"
+    elem = 4 if f32 else 8
+    nbytes = float(np.sum(p_in.astype(np.int64) * (p_in + 1) + p_out.astype(np.int64) * (p_out + 1))) * elem \
+        + 56.0 * n
+    desc = plan.describe()
+    plan.close()
+    return {"items": n, "per_s": n / t, "ms": round(t * 1e3, 4), "frac_hbm": nbytes / t / 1e9 / HBM_PEAK_GBS,
+            "plan_create_s": round(t_plan, 3),
+            "bins": [f"{b['mapping']}:{b['op']}:{b['bucket']}:{b['items']}" for b in desc["bins"]]}
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -224,13 +275,7 @@ def main():
 
     if not args.no_extra:
         # FP32 (normalised basis) at P=10 on the same multipoles
-        w = torch.ones(S, dtype=torch.float64, device=dev)
-        import math
-        for nn in range(P):
-            for m in range(nn + 1):
-                v = math.sqrt(math.factorial(nn + m) * math.factorial(nn - m))
-                w[nn * (nn + 1) + 2 * m] = v
-                w[nn * (nn + 1) + 2 * m + 1] = v
+        w = norm_weights(sh, torch, dev, P, 0)
         d_M32 = (d_M * w).float()
         d_r32 = d_r.float()
         d_L32 = torch.empty((n, S), dtype=torch.float32, device=dev)
@@ -243,6 +288,10 @@ def main():
         extra["m2l_p10_naive_f64_per_s"] = nv / t
         del d_M, d_L, d_M2, d_L2, I
         torch.cuda.empty_cache()
+        for dt, name in ((sh.SH_F64, "f64"), (sh.SH_F32, "f32")):
+            log(f"[bench] mixed-order list {name}")
+            extra[f"mixed_list_{name}"] = run_mixed(sh, ctx, torch, dev, dt)
+            torch.cuda.empty_cache()
         for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
             log(f"[bench] extra P={PP} n={nn_}")
             J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)

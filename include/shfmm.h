@@ -135,6 +135,67 @@ sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, i
                                void *out_pool, int64_t ld_out, unsigned flags,
                                void *hip_stream);
 
+/* ---------------- mixed work lists (batching across operations and orders) ----------------
+ * A work list mixes M2M, M2L and L2L translations of any orders (p_in != p_out allowed) in
+ * one call.  Item i reads the input solid at arena_in + items[i].in_off (p_in(p_in+1)
+ * reals of the plan's dtype) and writes arena_out + items[i].out_off (p_out(p_out+1)
+ * reals); offsets count reals and must be even.  The output solids of a list must not
+ * overlap one another nor any input solid of the list (overwrite and SH_ACCUMULATE
+ * alike), so the items are independent and the library may run them in any order.
+ * Dependent steps (an M2M feeding an M2L) go into successive lists. */
+typedef struct sh_item {
+    int32_t op;       /* SH_M2M, SH_M2L or SH_L2L */
+    int32_t p_in;     /* input order, 1..max order */
+    int32_t p_out;    /* output order, 1..max order */
+    int32_t reserved; /* must be 0 */
+    int64_t in_off;   /* input solid offset in the input arena, in reals, even, >= 0 */
+    int64_t out_off;  /* output solid offset in the output arena, in reals, even, >= 0 */
+    double r[3];      /* shift: output centre - input centre (FP64 for both dtypes) */
+} sh_item;
+
+typedef struct sh_plan sh_plan; /* opaque: a work list binned and uploaded for execution */
+
+#define SH_PLAN_AUTOTUNE 2u /* time the candidate kernel mappings of each bin at creation */
+#define SH_PLAN_NO_GRAPH 4u /* execute by plain launches instead of a replayed HIP graph */
+
+/* Bins a HOST array of `count` items by operation and order and uploads it (synchronous;
+ * allocates device memory owned by the plan).  Items of orders <= 16 run on the
+ * lane-per-translation kernel (64 translations per workgroup, orders rounded up to a
+ * bucket), larger orders on the one-wavefront-per-translation kernel; SH_PLAN_AUTOTUNE
+ * times the candidate mappings of each bin on zero-filled scratch arenas and keeps the
+ * fastest (decisions are cached per process and, when the environment variable
+ * SHFMM_TUNE_FILE names a file, in that file).  flags: SH_ACCUMULATE, SH_PLAN_AUTOTUNE,
+ * SH_PLAN_NO_GRAPH.  Errors: SH_EINVAL (null pointers, unknown op/dtype/flags, reserved
+ * != 0, odd or negative offset, overlapping outputs, an output overlapping an input),
+ * SH_EORDER, SH_ESHIFT (M2L shift zero or not finite, M2M/L2L shift not finite),
+ * SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_plan_create(sh_ctx *ctx, int dtype, const sh_item *items, int64_t count,
+                         unsigned flags, sh_plan **out);
+
+/* Runs a plan on DEVICE arenas of in_reals / out_reals reals (stream-ordered, returns
+ * after enqueue).  Unless SH_PLAN_NO_GRAPH was given, every bin's persistent kernel is
+ * captured once into a HIP graph (bins on parallel branches) and the graph is replayed,
+ * so one call is one graph launch; calling again with other arena pointers recaptures.
+ * Arenas must be aligned to two reals.  Calls on one plan are serialised by the plan.
+ * Errors: SH_EINVAL (null plan, null arena with a non-empty plan, misaligned arena, an
+ * item beyond in_reals / out_reals), SH_EDEVICE. */
+sh_status sh_plan_execute(sh_plan *plan, const void *arena_in, int64_t in_reals,
+                          void *arena_out, int64_t out_reals, void *hip_stream);
+
+/* Writes a JSON description of the plan's bins (kernel, operation, order bucket, items,
+ * tasks, whether the mapping was tuned) into buf (NUL-terminated, truncated to len);
+ * *needed (if not NULL) receives the full length including the NUL.  Errors: SH_EINVAL. */
+sh_status sh_plan_describe(const sh_plan *plan, char *buf, int64_t len, int64_t *needed);
+
+/* Waits for the plan's last execution and releases it.  NULL is accepted. */
+void sh_plan_destroy(sh_plan *plan);
+
+/* One-shot form: plan (no tuning, no graph), execute on hip_stream, wait for that
+ * stream, release.  Same arguments and errors as the three calls above. */
+sh_status sh_translate_list(sh_ctx *ctx, int dtype, const sh_item *items, int64_t count,
+                            const void *arena_in, int64_t in_reals, void *arena_out,
+                            int64_t out_reals, unsigned flags, void *hip_stream);
+
 /* ---------------- single translation (host pointers, synchronous) ----------------
  * The paper's statement of the problem: one input solid, one shift, one output solid.
  * Errors: SH_EINVAL, SH_EORDER, SH_ESHIFT (M2L with r = 0 or non-finite r), SH_EDEVICE. */

@@ -80,6 +80,7 @@ class Oracle:
             "or_direct": (ct, [i64, P, P, P]),
             "or_translate_batch": (None, [i32, i64, i32, i32, P, P, i64, P, i64, i32]),
             "or_p2m_batch": (None, [i64, i32, P, i64, P, P, P, i64, i32]),
+            "or_p2l_batch": (None, [i64, i32, P, i64, P, P, P, i64, i32]),
             "or_real_size": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -129,16 +130,21 @@ class Oracle:
         self._lib.or_p2l(P, cp, len(q), pp, qp, out.ctypes.data_as(self._P))
         return out
 
-    def p2m_batch(self, P, centres, pts, q, nthreads=1):
+    def _p2x_batch(self, fn, P, centres, pts, q, nthreads):
         centres, cp = self._arr(np.reshape(centres, (-1, 3)))
         count = centres.shape[0]
         pts, pp = self._arr(np.reshape(pts, (count, -1, 3)))
         npts = pts.shape[1]
         q, qp = self._arr(np.reshape(q, (count, npts)))
         out = np.zeros((count, self.size(P)), self.dtype)
-        self._lib.or_p2m_batch(count, P, cp, npts, pp, qp, out.ctypes.data_as(self._P),
-                               self.size(P), nthreads)
+        fn(count, P, cp, npts, pp, qp, out.ctypes.data_as(self._P), self.size(P), nthreads)
         return out
+
+    def p2m_batch(self, P, centres, pts, q, nthreads=1):
+        return self._p2x_batch(self._lib.or_p2m_batch, P, centres, pts, q, nthreads)
+
+    def p2l_batch(self, P, centres, pts, q, nthreads=1):
+        return self._p2x_batch(self._lib.or_p2l_batch, P, centres, pts, q, nthreads)
 
     # -- translations ----------------------------------------------------------
     def _tr(self, fn, p_in, p_out, r, C):

@@ -314,4 +314,13 @@ void or_p2m_batch(int64_t count, int P, const real *centres, int64_t npts, const
         or_p2m(P, centres + 3 * c, npts, pts + 3 * npts * c, q + npts * c, M + c * ldM);
 }
 
+/* P2L of many clusters (same layout as or_p2m_batch): local expansions about centres. */
+void or_p2l_batch(int64_t count, int P, const real *centres, int64_t npts, const real *pts,
+                  const real *q, real *L, int64_t ldL, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t c = 0; c < count; ++c)
+        or_p2l(P, centres + 3 * c, npts, pts + 3 * npts * c, q + npts * c, L + c * ldL);
+}
+
 int or_real_size(void) { return (int)sizeof(real); }

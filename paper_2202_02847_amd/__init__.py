@@ -22,6 +22,8 @@ SH_OK, SH_EINVAL, SH_EORDER, SH_ESHIFT, SH_ENOMEM, SH_EDEVICE, SH_EBUSY = 0, -1,
 SH_M2M, SH_M2L, SH_L2L = 0, 1, 2
 SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
+SH_PLAN_AUTOTUNE = 2
+SH_PLAN_NO_GRAPH = 4
 SH_MAX_ORDER = 64
 OPS = {"m2m": SH_M2M, "m2l": SH_M2L, "l2l": SH_L2L}
 
@@ -53,6 +55,11 @@ _SIGS = {
     "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
     "sh_normalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
     "sh_denormalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
+    "sh_plan_create": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _c_u32, ctypes.POINTER(_vp)]),
+    "sh_plan_execute": (_c_i32, [_vp, _vp, _c_i64, _vp, _c_i64, _vp]),
+    "sh_plan_describe": (_c_i32, [_vp, _vp, _c_i64, ctypes.POINTER(_c_i64)]),
+    "sh_plan_destroy": (None, [_vp]),
+    "sh_translate_list": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
 }
 for _op in ("m2l", "m2m", "l2l"):
     for _dt in ("f64", "f32"):
@@ -240,3 +247,91 @@ def sh_denormalise_f64(kind: int, P: int, solids: np.ndarray) -> np.ndarray:
     a2 = a.reshape(-1, a.shape[-1])
     _check(lib().sh_denormalise_f64(kind, P, a2.shape[0], a2.ctypes.data, a2.shape[1]), "sh_denormalise_f64")
     return a
+
+
+# ---------------- mixed work lists ----------------
+
+# numpy image of the C struct sh_item (56 bytes)
+SH_ITEM = np.dtype([("op", "<i4"), ("p_in", "<i4"), ("p_out", "<i4"), ("reserved", "<i4"),
+                    ("in_off", "<i8"), ("out_off", "<i8"), ("r", "<f8", (3,))], align=True)
+assert SH_ITEM.itemsize == 56
+
+
+def make_items(op, p_in, p_out, in_off, out_off, r) -> np.ndarray:
+    """Packs per-item arrays (broadcast) into an sh_item array."""
+    op = np.asarray(op)
+    n = np.broadcast(op, np.asarray(p_in), np.asarray(p_out), np.asarray(in_off), np.asarray(out_off)).shape
+    n = int(np.prod(n)) if n else 1
+    it = np.zeros(n, SH_ITEM)
+    it["op"] = op
+    it["p_in"] = p_in
+    it["p_out"] = p_out
+    it["in_off"] = in_off
+    it["out_off"] = out_off
+    it["r"] = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    return it
+
+
+class Plan:
+    """Owning wrapper of an ``sh_plan*`` (sh_plan_create / sh_plan_destroy)."""
+
+    def __init__(self, ctx, dtype: int, items: np.ndarray, flags: int = 0):
+        items = np.ascontiguousarray(items, dtype=SH_ITEM)
+        h = _vp()
+        _check(lib().sh_plan_create(_h(ctx), dtype, items.ctypes.data if len(items) else None, len(items), flags,
+                                    ctypes.byref(h)), "sh_plan_create")
+        self._h = h.value
+        self.ctx = ctx
+        self.dtype = dtype
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    def execute(self, arena_in, in_reals, arena_out, out_reals, stream=None):
+        _check(lib().sh_plan_execute(self.handle, _ptr(arena_in), in_reals, _ptr(arena_out), out_reals,
+                                     _stream(stream)), "sh_plan_execute")
+
+    def describe(self) -> dict:
+        import json
+        need = _c_i64()
+        _check(lib().sh_plan_describe(self.handle, None, 0, ctypes.byref(need)), "sh_plan_describe")
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().sh_plan_describe(self.handle, buf, need.value, None), "sh_plan_describe")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            lib().sh_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sh_plan_create(ctx, dtype, items, flags=0) -> Plan:
+    return Plan(ctx, dtype, items, flags)
+
+
+def sh_plan_execute(plan: Plan, arena_in, in_reals, arena_out, out_reals, stream=None) -> None:
+    plan.execute(arena_in, in_reals, arena_out, out_reals, stream)
+
+
+def sh_plan_describe(plan: Plan) -> dict:
+    return plan.describe()
+
+
+def sh_plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def sh_translate_list(ctx, dtype, items, arena_in, in_reals, arena_out, out_reals, flags=0, stream=None):
+    items = np.ascontiguousarray(items, dtype=SH_ITEM)
+    _check(lib().sh_translate_list(_h(ctx), dtype, items.ctypes.data if len(items) else None, len(items),
+                                   _ptr(arena_in), in_reals, _ptr(arena_out), out_reals, flags, _stream(stream)),
+           "sh_translate_list")

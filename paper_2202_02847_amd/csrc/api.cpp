@@ -12,34 +12,14 @@
 #include <vector>
 
 #include "../../include/shfmm.h"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 
-struct sh_ctx {
-    int device = -1;
-    int max_order = 0;
-    void *dev_mem = nullptr;     // one allocation holding every table
-    int *err_flag = nullptr;     // device int
-    shfmm::DevTables tabs{};
-};
-
 namespace {
 
+using shfmm::DeviceGuard;
 using shfmm::TransArgs;
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = (hipSetDevice(dev) == hipSuccess);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 bool valid_op(int op) { return op == SH_M2M || op == SH_M2L || op == SH_L2L; }
 bool valid_dtype(int d) { return d == SH_F64 || d == SH_F32; }

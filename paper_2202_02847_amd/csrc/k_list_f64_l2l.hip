@@ -1,0 +1,8 @@
+// Work-list lane-per-translation kernels: double, L2L, order buckets 4..16.
+#include "list_impl.hpp"
+
+namespace shfmm {
+namespace lpt {
+template hipError_t launch_list_fixed<double, double, OP_L2L>(int, const DevTables &, const ListArgs &, hipStream_t);
+}  // namespace lpt
+}  // namespace shfmm

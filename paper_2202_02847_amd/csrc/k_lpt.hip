@@ -4,7 +4,7 @@
 #include <mutex>
 #include <utility>
 
-#include "lpt_impl.hpp"
+#include "list_impl.hpp"
 
 namespace shfmm {
 
@@ -52,6 +52,30 @@ hipError_t launch_lpt(const DevTables &tab, const TransArgs &a, bool f32, hipStr
     if (a.op == OP_M2M) return launch_fixed<double, double, OP_M2M>(P, tab, a, s);
     if (a.op == OP_M2L) return launch_fixed<double, double, OP_M2L>(P, tab, a, s);
     return launch_fixed<double, double, OP_L2L>(P, tab, a, s);
+}
+
+}  // namespace shfmm
+
+namespace shfmm {
+
+const int *list_buckets(int *n)
+{
+    if (n) *n = (int)(sizeof(lpt::kListBuckets) / sizeof(lpt::kListBuckets[0]));
+    return lpt::kListBuckets;
+}
+
+hipError_t launch_list_lpt(const DevTables &tab, const ListArgs &la, int op, bool f32, int bucket, hipStream_t s)
+{
+    using namespace lpt;
+    if (la.ntasks <= 0) return hipSuccess;
+    if (f32) {
+        if (op == OP_M2M) return launch_list_fixed<float, float, OP_M2M>(bucket, tab, la, s);
+        if (op == OP_M2L) return launch_list_fixed<float, float, OP_M2L>(bucket, tab, la, s);
+        return launch_list_fixed<float, float, OP_L2L>(bucket, tab, la, s);
+    }
+    if (op == OP_M2M) return launch_list_fixed<double, double, OP_M2M>(bucket, tab, la, s);
+    if (op == OP_M2L) return launch_list_fixed<double, double, OP_M2L>(bucket, tab, la, s);
+    return launch_list_fixed<double, double, OP_L2L>(bucket, tab, la, s);
 }
 
 }  // namespace shfmm

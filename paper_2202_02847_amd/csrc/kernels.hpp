@@ -24,8 +24,47 @@ struct TransArgs {
     int *err;            // device error flag
 };
 
+// One item of a mixed work list (same layout as the public sh_item): operation, orders,
+// input / output offsets (in reals) into the caller's arena, shift.
+struct ListItem {
+    int32_t op, p_in, p_out, reserved;
+    int64_t in_off, out_off;
+    double r[3];
+};
+static_assert(sizeof(ListItem) == 56, "ListItem layout");
+
+// A task of the lane-per-translation list kernel: up to 64 consecutive items (of one op)
+// sharing (p_in, p_out).
+struct ListTask {
+    int32_t p_in, p_out;
+    int32_t count;
+    int32_t reserved;
+    int64_t first;
+};
+
+struct ListArgs {
+    const ListItem *items;
+    int64_t count;        // items (wavefront-per-item kernel)
+    const ListTask *tasks;
+    int64_t ntasks;       // tasks (lane-per-translation kernel)
+    const void *arena_in;
+    void *arena_out;
+    unsigned flags;
+    int *err;
+};
+
 // General rotation kernel: any orders up to the table order, one wavefront per translation.
 hipError_t launch_general(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s);
+
+// Work-list forms.  General: one wavefront per item, any op / orders (pmax = largest order
+// in the list, sizes the LDS).  Lane-per-translation: tasks of one op whose orders are at
+// most `bucket`; bucket must be one of list_buckets().
+hipError_t launch_list_general(const DevTables &tab, const ListArgs &la, bool f32, bool wide, int pmax,
+                               hipStream_t s);
+hipError_t launch_list_lpt(const DevTables &tab, const ListArgs &la, int op, bool f32, int bucket,
+                           hipStream_t s);
+// Order buckets of the lane-per-translation list kernel (ascending).
+const int *list_buckets(int *n);
 
 // Highest order with a fixed-order (lane-per-translation) kernel.
 constexpr int kLptMaxOrder = 16;

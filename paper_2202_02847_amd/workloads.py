@@ -12,7 +12,10 @@ Recipes (all coordinates relative to the expansion centre):
     uniform in [lo, hi];
   * octree M2L shift: one of the 316 integer offsets in [-3, 3]^3 with max-norm > 1 (the
     well-separated boxes of a uniform-octree level of unit box width);
-  * octree parent/child shift: one of the 8 offsets (+-1/4, +-1/4, +-1/4).
+  * octree parent/child shift: one of the 8 offsets (+-1/4, +-1/4, +-1/4);
+  * mixed work list: operation M2M / M2L / L2L with probabilities 0.2 / 0.6 / 0.2, input
+    and output orders drawn independently, 70% from U{6..12} and 30% from U{3..30}, a
+    random shift of length in [2, 6] for every operation.
 """
 from __future__ import annotations
 
@@ -94,3 +97,15 @@ def config2(n_m2l: int = 1 << 20, n_child: int = 1 << 17, npts: int = 32, P: int
     rc, _ = child_shifts(rng_for(seed_config, 2), n_child)
     rl, _ = child_shifts(rng_for(seed_config, 3), n_child)
     return {"P": P, "pts": pts, "q": q, "r_m2l": r, "dir_idx": idx, "r_m2m": rc, "r_l2l": rl}
+
+
+def config4(n: int = 500_000, npts: int = 20, lo: int = 3, hi: int = 30, seed_config: int = 4,
+            op_prob=(0.2, 0.6, 0.2)):
+    """Mixed-order work list: op codes (0 M2M, 1 M2L, 2 L2L), orders, shifts, and one
+    cluster per item (its source points)."""
+    op = rng_for(seed_config, 0).choice(3, size=n, p=list(op_prob)).astype(np.int32)
+    p_in = mixed_orders(rng_for(seed_config, 1), n, lo, hi).astype(np.int32)
+    p_out = mixed_orders(rng_for(seed_config, 2), n, lo, hi).astype(np.int32)
+    r = random_shifts(rng_for(seed_config, 3), n, 2.0, 6.0)
+    pts, q = clusters(rng_for(seed_config, 4), n, npts)
+    return {"op": op, "p_in": p_in, "p_out": p_out, "r": r, "pts": pts, "q": q}

@@ -336,6 +336,33 @@ def pin_l2l_after_m2l_vs_direct(o):
     return worst, 1e-8
 
 
+def pin_p2l_closed_form_and_near_field(o):
+    """P2L (eq. MLexpansions, local side): one charge q at y gives L_n^m = q S_n^m(y - x_B)
+    (closed form, Legendre); a cluster about 3.5 away, evaluated within 0.3 of x_B,
+    reproduces the direct potential (convergence ratio below 0.12 at P = 20); the batch
+    form equals the single calls."""
+    rng = _rng(47)
+    err = 0.0
+    P = 12
+    for _ in range(3):
+        y = _unit(rng) * rng.uniform(1.5, 3.0)
+        xb = rng.uniform(-0.3, 0.3, 3)
+        L = o.p2l(P, xb, [y], [0.45])
+        err = max(err, max_degree_error(L, 0.45 * singular_closed(y - xb, P), P, "L"))
+    P = 20
+    pts, q = _cluster(rng, 20, centre=_unit(rng) * 3.5)
+    L = o.p2l(P, [0, 0, 0], pts, q)
+    for _ in range(4):
+        t = _unit(rng) * 0.3
+        err = max(err, abs(o.eval_l(P, [0, 0, 0], L, t) - o.direct(pts, q, t)) / abs(o.direct(pts, q, t)))
+    centres = rng.uniform(-0.2, 0.2, (3, 3))
+    cl = [_cluster(rng, 7, centre=c + [2.5, 0, 1]) for c in centres]
+    Lb = o.p2l_batch(9, centres, np.stack([c[0] for c in cl]), np.stack([c[1] for c in cl]), nthreads=2)
+    for i, c in enumerate(centres):
+        err = max(err, _rel(Lb[i], o.p2l(9, c, cl[i][0], cl[i][1])))
+    return err, 1e-12
+
+
 # ---------------------------------------------------------------- evaluation
 def pin_eval_m_far_field(o):
     """The M expansion reproduces the direct potential outside the cluster, error ~ (a/|x|)^P."""
@@ -368,5 +395,6 @@ PINS = [
     pin_l2l_composition,
     pin_l2l_mixed_orders,
     pin_l2l_after_m2l_vs_direct,
+    pin_p2l_closed_form_and_near_field,
     pin_eval_m_far_field,
 ]
