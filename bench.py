@@ -129,6 +129,74 @@ def run_mixed(sh, ctx, torch, dev, dtype, n=500_000, reps=5):
             "bins": [f"{b['mapping']}:{b['op']}:{b['bucket']}:{b['items']}" for b in desc["bins"]]}
 
 
+def degree_error(got, ref, P):
+    """Per-translation max over degrees n of max_m |got - ref| / max_m |ref| (normalised basis)."""
+    worst = np.zeros(got.shape[0])
+    for n in range(P):
+        a, b = n * (n + 1), (n + 1) * (n + 2)
+        den = np.maximum(np.abs(ref[:, a:b]).max(axis=1), 1e-300)
+        worst = np.maximum(worst, np.abs(got[:, a:b] - ref[:, a:b]).max(axis=1) / den)
+    return worst
+
+
+def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
+    """Shared-direction M2L at order P: 2^20 translations grouped by the 316 octree offsets,
+    FP32 normalised solids.  Times the BF16x6 and BF16x3 matrix-core paths, the FP32 and
+    FP64 rotation paths on the same multipoles, and states each FP32 path's per-degree error
+    against the FP64 GPU path (itself held to 1e-12 of the oracle by the tests)."""
+    from paper_2202_02847_amd import workloads as wl
+
+    c = wl.config2(n_m2l=n, n_child=8, npts=32, P=P, seed_config=3)
+    order = np.argsort(c["dir_idx"], kind="stable")
+    offs = wl.octree_offsets()
+    counts = np.bincount(c["dir_idx"], minlength=len(offs))
+    S = solid(P)
+    d_pts = torch.from_numpy(np.ascontiguousarray(c["pts"][order])).to(dev)
+    d_q = torch.from_numpy(np.ascontiguousarray(c["q"][order])).to(dev)
+    d_r64 = torch.from_numpy(np.ascontiguousarray(c["r_m2l"][order])).to(dev)
+    del c
+    d_M = torch.empty((n, S), dtype=torch.float64, device=dev)
+    sh.sh_p2m_batch_f64(ctx, P, n, torch.zeros((n, 3), dtype=torch.float64, device=dev), d_pts.shape[1], d_pts,
+                        d_q, d_M, S)
+    del d_pts, d_q
+    wM, wL = norm_weights(sh, torch, dev, P, 0), norm_weights(sh, torch, dev, P, 1)
+    d_M32 = (d_M * wM).float()
+    d_cs = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).to(dev)
+    d_L64 = torch.empty((n, S), dtype=torch.float64, device=dev)
+    d_L32 = torch.empty((n, S), dtype=torch.float32, device=dev)
+    res = {"P": P, "translations": n, "classes": len(offs)}
+    t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, P, P, n, d_r64, d_M, S, d_L64, S), reps)
+    res["rot_f64_per_s"] = n / t
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    pick = torch.from_numpy(np.sort(rng.choice(n, sample, replace=False))).to(dev)
+    ref = (d_L64[pick] * wL).cpu().numpy()  # FP64 result in the normalised basis
+    d_r32 = d_r64.float()
+    t = time_launch(torch, lambda: sh.sh_m2l_batch_f32(ctx, P, P, n, d_r32, d_M32, S, d_L32, S), reps)
+    res["rot_f32_per_s"] = n / t
+    e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
+    res["rot_f32_err_max"], res["rot_f32_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
+    bpt = bytes_per_translation(P, P, 4) - 12  # FP32 solids in and out, no shift array
+    for prec, name in ((sh.SH_SHARED_BF16X6, "bf16x6"), (sh.SH_SHARED_BF16X3, "bf16x3")):
+        t0 = time.perf_counter()
+        op = sh.Shared(ctx, "m2l", P, P, offs, prec)
+        res[f"{name}_build_s"] = round(time.perf_counter() - t0, 3)
+        res[f"{name}_operator_bytes"] = op.nbytes()
+        d_L32.zero_()
+        t = time_launch(torch, lambda: op.execute(n, d_cs, d_M32, S, d_L32, S), reps)
+        products = 6 if prec == sh.SH_SHARED_BF16X6 else 3
+        res[f"{name}_per_s"] = n / t
+        res[f"{name}_ms"] = round(t * 1e3, 4)
+        res[f"{name}_frac_mfma_bf16"] = 2.0 * S * S * products * n / t / 2.5e15
+        res[f"{name}_frac_hbm"] = bpt * n / t / 1e9 / HBM_PEAK_GBS
+        e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
+        res[f"{name}_err_max"], res[f"{name}_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
+        op.close()
+    del d_M, d_M32, d_L64, d_L32
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -287,6 +355,9 @@ def main():
         t = time_launch(torch, lambda: sh.sh_m2l_naive_batch_f64(ctx, P, P, nv, d_r, d_M, S, d_L, S), 3)
         extra["m2l_p10_naive_f64_per_s"] = nv / t
         del d_M, d_L, d_M2, d_L2, I
+        torch.cuda.empty_cache()
+        log("[bench] shared-direction precision forms P=16")
+        extra["precision_p16"] = run_precision(sh, ctx, torch, dev)
         torch.cuda.empty_cache()
         for dt, name in ((sh.SH_F64, "f64"), (sh.SH_F32, "f32")):
             log(f"[bench] mixed-order list {name}")

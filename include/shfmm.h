@@ -196,6 +196,46 @@ sh_status sh_translate_list(sh_ctx *ctx, int dtype, const sh_item *items, int64_
                             const void *arena_in, int64_t in_reals, void *arena_out,
                             int64_t out_reals, unsigned flags, void *hip_stream);
 
+/* ---------------- shared-shift translations on the matrix cores ----------------
+ * Translations that share one shift vector (the fixed offsets of a uniform octree level:
+ * the 316 well-separated M2L offsets, the 8 parent/child offsets) apply the same linear
+ * map: every step of the rotation scheme (Section 3.4) depends on the shift only, so the
+ * class's translation is one dense real matrix of p_out(p_out+1) x p_in(p_in+1) in the
+ * normalised basis.  sh_shared_create generates these matrices on the device in FP64 (the
+ * FP64 rotation kernels applied to unit solids), splits each entry into BF16 pieces and
+ * keeps them (sh_shared_bytes tells how much device memory).  sh_shared_execute applies
+ * them to FP32 normalised-basis solids as a grouped GEMM on MFMA with FP32 accumulation:
+ *   SH_SHARED_BF16X3: a_hi b_hi + a_hi b_mid + a_mid b_hi (about 16 significant bits;
+ *                     per-degree error ~1e-5 .. 1e-4);
+ *   SH_SHARED_BF16X6: adds a_hi b_lo + a_mid b_mid + a_lo b_hi (about FP32: ~1e-6).
+ * The FP32 solids use the layout and normalised basis of the FP32 batched calls. */
+typedef struct sh_shared sh_shared;
+
+#define SH_SHARED_BF16X3 3
+#define SH_SHARED_BF16X6 6
+
+/* Builds the operators of `nclass` (1..4096) shifts (host array, nclass x 3 doubles) for
+ * operation op and orders p_in -> p_out (synchronous; allocates device memory owned by the
+ * object).  Errors: SH_EINVAL, SH_EORDER, SH_ESHIFT (a non-finite shift, an M2L shift of
+ * zero), SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_shared_create(sh_ctx *ctx, int op, int p_in, int p_out, int nclass, const double *shifts,
+                           int precision, sh_shared **out);
+
+/* Applies the operators to `count` FP32 solids grouped by class: class c owns the
+ * translations i in [class_start[c], class_start[c+1]) (DEVICE array of nclass + 1 int64,
+ * non-decreasing, from 0 to count; values outside [0, count] are clamped), which read
+ * in + i*ld_in and write out + i*ld_out.  ld_in even and in 8-byte aligned.  flags: 0 or
+ * SH_ACCUMULATE.  Stream-ordered, allocates nothing.  Errors: SH_EINVAL, SH_EDEVICE. */
+sh_status sh_shared_execute(const sh_shared *shared, int64_t count, const int64_t *class_start,
+                            const float *in, int64_t ld_in, float *out, int64_t ld_out,
+                            unsigned flags, void *hip_stream);
+
+/* Device bytes held by the operators (-1 for NULL). */
+int64_t sh_shared_bytes(const sh_shared *shared);
+
+/* Releases the operators.  NULL is accepted. */
+void sh_shared_destroy(sh_shared *shared);
+
 /* ---------------- single translation (host pointers, synchronous) ----------------
  * The paper's statement of the problem: one input solid, one shift, one output solid.
  * Errors: SH_EINVAL, SH_EORDER, SH_ESHIFT (M2L with r = 0 or non-finite r), SH_EDEVICE. */

@@ -24,6 +24,8 @@ SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
 SH_PLAN_AUTOTUNE = 2
 SH_PLAN_NO_GRAPH = 4
+SH_SHARED_BF16X3 = 3
+SH_SHARED_BF16X6 = 6
 SH_MAX_ORDER = 64
 OPS = {"m2m": SH_M2M, "m2l": SH_M2L, "l2l": SH_L2L}
 
@@ -60,6 +62,10 @@ _SIGS = {
     "sh_plan_describe": (_c_i32, [_vp, _vp, _c_i64, ctypes.POINTER(_c_i64)]),
     "sh_plan_destroy": (None, [_vp]),
     "sh_translate_list": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
+    "sh_shared_create": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _c_i32, ctypes.POINTER(_vp)]),
+    "sh_shared_execute": (_c_i32, [_vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
+    "sh_shared_bytes": (_c_i64, [_vp]),
+    "sh_shared_destroy": (None, [_vp]),
 }
 for _op in ("m2l", "m2m", "l2l"):
     for _dt in ("f64", "f32"):
@@ -335,3 +341,58 @@ def sh_translate_list(ctx, dtype, items, arena_in, in_reals, arena_out, out_real
     _check(lib().sh_translate_list(_h(ctx), dtype, items.ctypes.data if len(items) else None, len(items),
                                    _ptr(arena_in), in_reals, _ptr(arena_out), out_reals, flags, _stream(stream)),
            "sh_translate_list")
+
+
+# ---------------- shared-shift operators (matrix cores) ----------------
+
+class Shared:
+    """Owning wrapper of an ``sh_shared*`` (sh_shared_create / sh_shared_destroy)."""
+
+    def __init__(self, ctx, op, p_in, p_out, shifts, precision=SH_SHARED_BF16X6):
+        shifts = np.ascontiguousarray(np.reshape(shifts, (-1, 3)), dtype=np.float64)
+        h = _vp()
+        _check(lib().sh_shared_create(_h(ctx), OPS.get(op, op), p_in, p_out, shifts.shape[0], shifts.ctypes.data,
+                                      precision, ctypes.byref(h)), "sh_shared_create")
+        self._h = h.value
+        self.nclass = shifts.shape[0]
+        self.p_in, self.p_out = p_in, p_out
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("shared operators destroyed")
+        return self._h
+
+    def execute(self, count, class_start, inp, ld_in, out, ld_out, flags=0, stream=None):
+        _check(lib().sh_shared_execute(self.handle, count, _ptr(class_start), _ptr(inp), ld_in, _ptr(out), ld_out,
+                                       flags, _stream(stream)), "sh_shared_execute")
+
+    def nbytes(self) -> int:
+        return int(lib().sh_shared_bytes(self.handle))
+
+    def close(self):
+        if self._h:
+            lib().sh_shared_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sh_shared_create(ctx, op, p_in, p_out, shifts, precision=SH_SHARED_BF16X6) -> Shared:
+    return Shared(ctx, op, p_in, p_out, shifts, precision)
+
+
+def sh_shared_execute(shared: Shared, count, class_start, inp, ld_in, out, ld_out, flags=0, stream=None) -> None:
+    shared.execute(count, class_start, inp, ld_in, out, ld_out, flags, stream)
+
+
+def sh_shared_bytes(shared: Shared) -> int:
+    return shared.nbytes()
+
+
+def sh_shared_destroy(shared: Shared) -> None:
+    shared.close()

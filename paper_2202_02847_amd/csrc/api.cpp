@@ -42,6 +42,8 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
     if (st != SH_OK) return st;
     if (count == 0) return SH_OK;
     if (!r || !in || !out) return SH_EINVAL;
+    // the indexed kernels read both index arrays
+    if ((src == nullptr) != (dst == nullptr)) return SH_EINVAL;
     DeviceGuard g(ctx->device);
     if (!g.ok) return SH_EDEVICE;
     TransArgs a;
@@ -129,6 +131,19 @@ sh_status scale_solids(int kind, int P, int64_t count, double *solids, int64_t l
 }
 
 }  // namespace
+
+namespace shfmm {
+
+sh_status translate_device(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                           const void *r, const int64_t *src, const void *in, int64_t ld_in,
+                           const int64_t *dst, void *out, int64_t ld_out, unsigned flags, void *stream)
+{
+    return launch(ctx, op, dtype, p_in, p_out, count, r, src, in, ld_in, dst, out, ld_out, flags, stream);
+}
+
+long double norm_weight(int n, int m) { return weight(n, m); }
+
+}  // namespace shfmm
 
 extern "C" {
 

@@ -33,4 +33,13 @@ struct DeviceGuard {
     DeviceGuard &operator=(const DeviceGuard &) = delete;
 };
 
+// Batched translation on device pointers (the dispatch behind sh_translate_batch /
+// sh_translate_indexed, for use inside the library).
+sh_status translate_device(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                           const void *r, const int64_t *src, const void *in, int64_t ld_in,
+                           const int64_t *dst, void *out, int64_t ld_out, unsigned flags, void *stream);
+
+// Normalisation weight w_n^m = sqrt((n+m)! (n-m)!) in extended precision.
+long double norm_weight(int n, int m);
+
 }  // namespace shfmm

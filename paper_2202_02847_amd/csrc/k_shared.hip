@@ -1,0 +1,267 @@
+// Shared-shift translations on the matrix cores.
+//
+// For translations that share one shift vector (the fixed offsets of a uniform octree level:
+// 316 M2L offsets, 8 parent/child offsets) every step of the rotation scheme of Section 3.4
+// (scalings, z-rotations, swaps, z-translation) is the same linear map, so the translation
+// of the whole class is one real matrix T_c (p_out(p_out+1) x p_in(p_in+1)) in the
+// normalised basis, applied to every solid of the class: a dense contraction.  The
+// operators are generated on the device in FP64 (the rotation kernels applied to unit
+// solids), split into BF16 pieces, and applied by a grouped GEMM on MFMA with FP32
+// accumulation:
+//   x3: a_hi b_hi + a_hi b_mid + a_mid b_hi          (about 16 significant bits)
+//   x6: x3 + a_hi b_lo + a_mid b_mid + a_lo b_hi       (about FP32 accuracy)
+// where a = a_hi + a_mid + a_lo is the FP32 input and b the FP64 operator entry, each piece
+// a BF16 number (8 significant bits).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace shfmm {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// round to nearest even; Inf and NaN stay Inf and NaN
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+constexpr int kTM = 64;    // translations per work item (4 MFMA row tiles)
+constexpr int kKC = 128;   // K (input reals) per LDS chunk
+constexpr int kLDA = kKC + 4;
+constexpr int kNTW = 5;    // output tiles of 16 per wavefront and work item
+constexpr int kNTC = 4 * kNTW;
+constexpr int kMaxClasses = 4096;
+
+// ---------------------------------------------------------------------------------------
+// Operator preparation: T_raw[c][k][n] (FP64, paper basis, row k = image of unit solid k)
+// -> normalised entries split into BF16 pieces, stored in B-operand fragment order:
+// frag[c][piece][nt][ks][lane][j] holds B[k][n] with k = 32 ks + 8 (lane / 16) + j and
+// n = 16 nt + lane % 16 (zero outside k < K, n < N).
+// ---------------------------------------------------------------------------------------
+__global__ void k_shared_prep(const double *__restrict__ traw, int64_t nclass, int K, int N, int KS, int NT,
+                              int npieces, const double *__restrict__ s_in, const double *__restrict__ s_out,
+                              unsigned short *__restrict__ frag)
+{
+    const int64_t per_class = (int64_t)NT * KS * 64 * 8;
+    const int64_t total = nclass * per_class;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / per_class;
+        int64_t rest = e - c * per_class;
+        const int j = (int)(rest & 7);
+        const int lane = (int)((rest >> 3) & 63);
+        rest >>= 9;
+        const int ks = (int)(rest % KS);
+        const int nt = (int)(rest / KS);
+        const int k = 32 * ks + 8 * (lane >> 4) + j;
+        const int n = 16 * nt + (lane & 15);
+        double t = 0.0;
+        if (k < K && n < N) t = traw[(c * K + k) * N + n] * s_out[n] / s_in[k];
+        unsigned short p[3];
+        double rem = t;
+        for (int q = 0; q < 3; ++q) {
+            p[q] = bf16_bits((float)rem);
+            rem -= (double)bf16_value(p[q]);
+        }
+        const int64_t slot = ((int64_t)nt * KS + ks) * 512 + lane * 8 + j;
+        for (int q = 0; q < npieces; ++q) frag[(c * npieces + q) * per_class + slot] = p[q];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Grouped GEMM.  Work item = (class c, 64 consecutive translations of c, a chunk of up to
+// 20 output tiles of 16).  The FP32 input rows of the 64 translations pass through LDS in
+// K chunks of 128; every wavefront multiplies them with its 5 output tiles' operator
+// fragments (read from global memory / L2, shared by every work item of the class).
+// ---------------------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
+{
+    constexpr int NPB = PREC == 6 ? 3 : 2;
+    __shared__ float As[kTM * kLDA];
+    __shared__ int tiles_before[kMaxClasses + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nclass = a.nclass;
+    const int64_t count = a.count;
+
+    // work items per class: ceil(rows / 64) x N chunks (prefix sum in LDS)
+    const int nchunks = (a.NT + kNTC - 1) / kNTC;
+    if (wave == 0) {
+        int carry = 0;
+        for (int c0 = 0; c0 < nclass; c0 += 64) {
+            const int c = c0 + lane;
+            int v = 0;
+            if (c < nclass) {
+                int64_t s0 = a.class_start[c], s1 = a.class_start[c + 1];
+                s0 = s0 < 0 ? 0 : (s0 > count ? count : s0);
+                s1 = s1 < s0 ? s0 : (s1 > count ? count : s1);
+                v = (int)((s1 - s0 + kTM - 1) / kTM) * nchunks;
+            }
+            // inclusive wave prefix sum
+            for (int d = 1; d < 64; d <<= 1) {
+                const int u = __shfl_up(v, d);
+                if (lane >= d) v += u;
+            }
+            if (c < nclass) tiles_before[c + 1] = carry + v;
+            carry += __shfl(v, 63);
+        }
+        if (lane == 0) tiles_before[0] = 0;
+    }
+    __syncthreads();
+    const int total = tiles_before[nclass];
+
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        // class of this work item (binary search over the prefix)
+        int lo = 0, hi = nclass - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tiles_before[mid] <= w) lo = mid; else hi = mid - 1;
+        }
+        const int c = lo;
+        const int local = w - tiles_before[c];
+        const int mtile = local / nchunks, chunk = local - mtile * nchunks;
+        int64_t s0 = a.class_start[c], s1 = a.class_start[c + 1];
+        s0 = s0 < 0 ? 0 : (s0 > count ? count : s0);
+        s1 = s1 < s0 ? s0 : (s1 > count ? count : s1);
+        const int64_t first = s0 + (int64_t)mtile * kTM;
+        const int rows = (int)((s1 - first) < kTM ? (s1 - first) : kTM);
+        const int nt0 = chunk * kNTC;
+
+        f32x4 acc[4][kNTW];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int t = 0; t < kNTW; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        for (int kc = 0; kc < a.Kp; kc += kKC) {
+            const int kw = (a.Kp - kc) < kKC ? (a.Kp - kc) : kKC;  // multiple of 32
+            // stage 64 input rows x kw reals (pairs; rows past the class re-read its last row)
+            __syncthreads();
+            for (int p = tid; p < kTM * (kw / 2); p += 256) {
+                const int t = p / (kw / 2);
+                const int k = kc + 2 * (p - t * (kw / 2));
+                const int64_t row = first + (t < rows ? t : rows - 1);
+                float2 v = make_float2(0.f, 0.f);
+                if (k < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k);
+                if (!a.live_in[k]) v.x = 0.f;
+                if (!a.live_in[k + 1]) v.y = 0.f;
+                *reinterpret_cast<float2 *>(&As[t * kLDA + (k - kc)]) = v;
+            }
+            __syncthreads();
+            for (int ks = 0; ks < kw / 32; ++ks) {
+                const int kglob = (kc >> 5) + ks;
+                // B fragments of this wave's output tiles (nt = nt0 + wave + 4 i)
+                s16x8 b[kNTW][NPB];
+#pragma unroll
+                for (int i = 0; i < kNTW; ++i) {
+                    const int nt = nt0 + wave + 4 * i;
+                    const int ntc = nt < a.NT ? nt : a.NT - 1;
+#pragma unroll
+                    for (int q = 0; q < NPB; ++q) {
+                        const unsigned short *fp = a.frag + ((int64_t)c * NPB + q) * a.frag_class_stride +
+                                                   ((int64_t)ntc * a.KS + kglob) * 512 + lane * 8;
+                        b[i][q] = *reinterpret_cast<const s16x8 *>(fp);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    if (mt * 16 >= rows) break;
+                    // A fragment: row 16 mt + lane % 16, k = 32 ks + 8 (lane / 16) + j
+                    const float *ap = &As[(mt * 16 + (lane & 15)) * kLDA + 32 * ks + 8 * (lane >> 4)];
+                    const float4 x0 = *reinterpret_cast<const float4 *>(ap);
+                    const float4 x1 = *reinterpret_cast<const float4 *>(ap + 4);
+                    const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                    s16x8 ah, am, al;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const unsigned short h = bf16_bits(xv[j]);
+                        const float r1 = xv[j] - bf16_value(h);
+                        const unsigned short m = bf16_bits(r1);
+                        ah[j] = (short)h;
+                        am[j] = (short)m;
+                        if (PREC == 6) al[j] = (short)bf16_bits(r1 - bf16_value(m));
+                    }
+#pragma unroll
+                    for (int i = 0; i < kNTW; ++i) {
+                        if (nt0 + wave + 4 * i >= a.NT) break;
+                        f32x4 d = acc[mt][i];
+                        if (PREC == 6) {
+                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
+                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, am), __builtin_bit_cast(bf16x8, b[i][1]), d, 0, 0, 0);
+                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][2]), d, 0, 0, 0);
+                        }
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, am), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][1]), d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
+                        acc[mt][i] = d;
+                    }
+                }
+            }
+        }
+        // store: D row (translation) 16 mt + 4 (lane / 16) + j, column (output) 16 nt + lane % 16
+        const bool accumulate = (a.flags & 1u) != 0;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+            for (int i = 0; i < kNTW; ++i) {
+                const int n = (nt0 + wave + 4 * i) * 16 + (lane & 15);
+                if (n >= a.N) continue;
+                const bool live = a.live_out[n] != 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t = mt * 16 + 4 * (lane >> 4) + j;
+                    if (t >= rows) continue;
+                    float *o = a.out + (first + t) * a.ld_out + n;
+                    float v = live ? acc[mt][i][j] : 0.f;
+                    if (accumulate && live) v += *o;
+                    *o = v;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_shared_prep(const double *traw, int64_t nclass, int K, int N, int KS, int NT, int npieces,
+                              const double *s_in, const double *s_out, unsigned short *frag, hipStream_t s)
+{
+    const int64_t total = nclass * (int64_t)NT * KS * 512;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_shared_prep, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, traw,
+                       nclass, K, N, KS, NT, npieces, s_in, s_out, frag);
+    return hipGetLastError();
+}
+
+int shared_max_classes() { return kMaxClasses; }
+
+hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s)
+{
+    if (a.count <= 0 || a.nclass <= 0) return hipSuccess;
+    const void *fn = prec == 6 ? reinterpret_cast<const void *>(&k_shared_gemm<6>)
+                               : reinterpret_cast<const void *>(&k_shared_gemm<3>);
+    const int res = lpt::resident_workgroups(fn);
+    // enough work items for the whole batch, capped at the resident count (persistent loop)
+    const int nchunks = (a.NT + kNTC - 1) / kNTC;
+    const int64_t upper = ((a.count + kTM - 1) / kTM + a.nclass) * nchunks;
+    const dim3 grid((unsigned)(upper < res ? upper : res)), block(256);
+    if (prec == 6)
+        hipLaunchKernelGGL(k_shared_gemm<6>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(k_shared_gemm<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace shfmm

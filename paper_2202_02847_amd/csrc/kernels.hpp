@@ -66,6 +66,33 @@ hipError_t launch_list_lpt(const DevTables &tab, const ListArgs &la, int op, boo
 // Order buckets of the lane-per-translation list kernel (ascending).
 const int *list_buckets(int *n);
 
+// Shared-shift grouped GEMM (k_shared.hip): translations grouped by class, class c owning
+// rows [class_start[c], class_start[c+1]) of the FP32 input / output arrays.
+struct SharedArgs {
+    int64_t count;
+    int nclass;
+    int K, Kp, N, NT, KS;           // input reals, K padded to 32, output reals, output tiles, K steps
+    const int64_t *class_start;     // device, nclass + 1
+    const float *in;
+    int64_t ld_in;
+    float *out;
+    int64_t ld_out;
+    const unsigned short *frag;     // operator fragments (BF16 pieces)
+    int64_t frag_class_stride;      // elements per (class, piece)
+    const unsigned char *live_in;   // Kp flags: input real used (not Im C_n^0, not padding)
+    const unsigned char *live_out;  // N flags: output real not Im C_n^0
+    unsigned flags;                 // bit 0: accumulate
+};
+hipError_t launch_shared_prep(const double *traw, int64_t nclass, int K, int N, int KS, int NT, int npieces,
+                              const double *s_in, const double *s_out, unsigned short *frag, hipStream_t s);
+hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s);
+int shared_max_classes();
+
+namespace lpt {
+// Workgroups resident at once on the current device for kernel fn (CU count x occupancy).
+int resident_workgroups(const void *fn);
+}
+
 // Highest order with a fixed-order (lane-per-translation) kernel.
 constexpr int kLptMaxOrder = 16;
 
