@@ -38,7 +38,6 @@ __device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as
 
 constexpr int kTM = 64;    // translations per work item (4 MFMA row tiles)
 constexpr int kKC = 128;   // K (input reals) per LDS chunk
-constexpr int kLDA = kKC + 4;
 constexpr int kNTW = 5;    // output tiles of 16 per wavefront and work item
 constexpr int kNTC = 4 * kNTW;
 constexpr int kMaxClasses = 4096;
@@ -80,15 +79,22 @@ __global__ void k_shared_prep(const double *__restrict__ traw, int64_t nclass, i
 
 // ---------------------------------------------------------------------------------------
 // Grouped GEMM.  Work item = (class c, 64 consecutive translations of c, a chunk of up to
-// 20 output tiles of 16).  The FP32 input rows of the 64 translations pass through LDS in
-// K chunks of 128; every wavefront multiplies them with its 5 output tiles' operator
-// fragments (read from global memory / L2, shared by every work item of the class).
+// 20 output tiles of 16).  The FP32 input rows of the 64 translations are split into BF16
+// pieces once per K chunk of 128 and staged in LDS; wavefront w owns output tiles
+// w, w + 4, ..., w + 16 of the chunk and multiplies them with the operator fragments, read
+// from global memory (L2-resident: shared by every work item of the class) one K step ahead.
+// The MFMAs are issued product by product over 20 independent accumulators.
 // ---------------------------------------------------------------------------------------
 template <int PREC>
 __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
 {
-    constexpr int NPB = PREC == 6 ? 3 : 2;
-    __shared__ float As[kTM * kLDA];
+    constexpr int NPB = PREC == 6 ? 3 : 2;   // operator pieces
+    constexpr int NPA = PREC == 6 ? 3 : 2;   // input pieces
+    constexpr int NPROD = PREC == 6 ? 6 : 3;
+    // products, smallest first: (input piece, operator piece)
+    constexpr int PA[6] = {PREC == 6 ? 2 : 1, PREC == 6 ? 1 : 0, 0, 1, 0, 0};
+    constexpr int PB[6] = {PREC == 6 ? 0 : 0, PREC == 6 ? 1 : 1, PREC == 6 ? 2 : 0, 0, 1, 0};
+    __shared__ s16x8 Ap[NPA][kTM][kKC / 8 + 1];   // BF16 pieces, rows padded by one 16-byte slot
     __shared__ int tiles_before[kMaxClasses + 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -108,7 +114,6 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
                 s1 = s1 < s0 ? s0 : (s1 > count ? count : s1);
                 v = (int)((s1 - s0 + kTM - 1) / kTM) * nchunks;
             }
-            // inclusive wave prefix sum
             for (int d = 1; d < 64; d <<= 1) {
                 const int u = __shfl_up(v, d);
                 if (lane >= d) v += u;
@@ -122,7 +127,6 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
     const int total = tiles_before[nclass];
 
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
-        // class of this work item (binary search over the prefix)
         int lo = 0, hi = nclass - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -137,6 +141,14 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
         const int64_t first = s0 + (int64_t)mtile * kTM;
         const int rows = (int)((s1 - first) < kTM ? (s1 - first) : kTM);
         const int nt0 = chunk * kNTC;
+        // this wave's output tiles (tiles past the end re-read the last one; not stored)
+        const unsigned short *bptr[kNTW];
+#pragma unroll
+        for (int i = 0; i < kNTW; ++i) {
+            const int nt = nt0 + wave + 4 * i;
+            const int ntc = nt < a.NT ? nt : a.NT - 1;
+            bptr[i] = a.frag + (int64_t)c * NPB * a.frag_class_stride + (int64_t)ntc * a.KS * 512 + lane * 8;
+        }
 
         f32x4 acc[4][kNTW];
 #pragma unroll
@@ -144,69 +156,77 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
 #pragma unroll
             for (int t = 0; t < kNTW; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+        // operator fragments of K step 0
+        s16x8 bcur[kNTW][NPB];
+#pragma unroll
+        for (int i = 0; i < kNTW; ++i)
+#pragma unroll
+            for (int q = 0; q < NPB; ++q)
+                bcur[i][q] = *reinterpret_cast<const s16x8 *>(bptr[i] + q * a.frag_class_stride);
+
         for (int kc = 0; kc < a.Kp; kc += kKC) {
             const int kw = (a.Kp - kc) < kKC ? (a.Kp - kc) : kKC;  // multiple of 32
-            // stage 64 input rows x kw reals (pairs; rows past the class re-read its last row)
+            // split 64 input rows x kw reals into BF16 pieces in LDS (8 reals per thread step;
+            // rows past the class re-read its last row)
             __syncthreads();
-            for (int p = tid; p < kTM * (kw / 2); p += 256) {
-                const int t = p / (kw / 2);
-                const int k = kc + 2 * (p - t * (kw / 2));
+            for (int p = tid; p < kTM * (kw / 8); p += 256) {
+                const int t = p / (kw / 8);
+                const int k8 = p - t * (kw / 8);
+                const int k = kc + 8 * k8;
                 const int64_t row = first + (t < rows ? t : rows - 1);
-                float2 v = make_float2(0.f, 0.f);
-                if (k < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k);
-                if (!a.live_in[k]) v.x = 0.f;
-                if (!a.live_in[k + 1]) v.y = 0.f;
-                *reinterpret_cast<float2 *>(&As[t * kLDA + (k - kc)]) = v;
+                float x[8];
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    float2 v = make_float2(0.f, 0.f);
+                    if (k + j < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k + j);
+                    x[j] = a.live_in[k + j] ? v.x : 0.f;
+                    x[j + 1] = a.live_in[k + j + 1] ? v.y : 0.f;
+                }
+                s16x8 h, m, l;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const unsigned short hb = bf16_bits(x[j]);
+                    const float r1 = x[j] - bf16_value(hb);
+                    const unsigned short mb = bf16_bits(r1);
+                    h[j] = (short)hb;
+                    m[j] = (short)mb;
+                    l[j] = (short)bf16_bits(r1 - bf16_value(mb));
+                }
+                Ap[0][t][k8] = h;
+                Ap[1][t][k8] = m;
+                if (NPA == 3) Ap[NPA - 1][t][k8] = l;
             }
             __syncthreads();
             for (int ks = 0; ks < kw / 32; ++ks) {
                 const int kglob = (kc >> 5) + ks;
-                // B fragments of this wave's output tiles (nt = nt0 + wave + 4 i)
-                s16x8 b[kNTW][NPB];
+                // next K step's operator fragments, in flight during this step's MFMAs
+                const int knext = kglob + 1 < a.KS ? kglob + 1 : kglob;
+                s16x8 bnext[kNTW][NPB];
 #pragma unroll
-                for (int i = 0; i < kNTW; ++i) {
-                    const int nt = nt0 + wave + 4 * i;
-                    const int ntc = nt < a.NT ? nt : a.NT - 1;
+                for (int i = 0; i < kNTW; ++i)
 #pragma unroll
-                    for (int q = 0; q < NPB; ++q) {
-                        const unsigned short *fp = a.frag + ((int64_t)c * NPB + q) * a.frag_class_stride +
-                                                   ((int64_t)ntc * a.KS + kglob) * 512 + lane * 8;
-                        b[i][q] = *reinterpret_cast<const s16x8 *>(fp);
-                    }
-                }
+                    for (int q = 0; q < NPB; ++q)
+                        bnext[i][q] = *reinterpret_cast<const s16x8 *>(bptr[i] + q * a.frag_class_stride +
+                                                                       (int64_t)knext * 512);
+                // input fragments: row 16 mt + lane % 16, k = 32 ks + 8 (lane / 16) + j
+                s16x8 af[NPA][4];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    if (mt * 16 >= rows) break;
-                    // A fragment: row 16 mt + lane % 16, k = 32 ks + 8 (lane / 16) + j
-                    const float *ap = &As[(mt * 16 + (lane & 15)) * kLDA + 32 * ks + 8 * (lane >> 4)];
-                    const float4 x0 = *reinterpret_cast<const float4 *>(ap);
-                    const float4 x1 = *reinterpret_cast<const float4 *>(ap + 4);
-                    const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-                    s16x8 ah, am, al;
+                for (int q = 0; q < NPA; ++q)
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const unsigned short h = bf16_bits(xv[j]);
-                        const float r1 = xv[j] - bf16_value(h);
-                        const unsigned short m = bf16_bits(r1);
-                        ah[j] = (short)h;
-                        am[j] = (short)m;
-                        if (PREC == 6) al[j] = (short)bf16_bits(r1 - bf16_value(m));
-                    }
+                    for (int mt = 0; mt < 4; ++mt) af[q][mt] = Ap[q][mt * 16 + (lane & 15)][4 * ks + (lane >> 4)];
 #pragma unroll
-                    for (int i = 0; i < kNTW; ++i) {
-                        if (nt0 + wave + 4 * i >= a.NT) break;
-                        f32x4 d = acc[mt][i];
-                        if (PREC == 6) {
-                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
-                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, am), __builtin_bit_cast(bf16x8, b[i][1]), d, 0, 0, 0);
-                            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][2]), d, 0, 0, 0);
-                        }
-                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, am), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][1]), d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, b[i][0]), d, 0, 0, 0);
-                        acc[mt][i] = d;
-                    }
-                }
+                for (int pr = 0; pr < NPROD; ++pr)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int i = 0; i < kNTW; ++i)
+                            acc[mt][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, af[PA[pr]][mt]), __builtin_bit_cast(bf16x8, bcur[i][PB[pr]]),
+                                acc[mt][i], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < kNTW; ++i)
+#pragma unroll
+                    for (int q = 0; q < NPB; ++q) bcur[i][q] = bnext[i][q];
             }
         }
         // store: D row (translation) 16 mt + 4 (lane / 16) + j, column (output) 16 nt + lane % 16
