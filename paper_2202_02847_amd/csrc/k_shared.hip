@@ -41,6 +41,7 @@ constexpr int kKC = 128;   // K (input reals) per LDS chunk
 constexpr int kNTW = 5;    // output tiles of 16 per wavefront and work item
 constexpr int kNTC = 4 * kNTW;
 constexpr int kMaxClasses = 4096;
+constexpr int kMaxK = 64 * 65 + 32;  // input reals of order 64, padded
 
 // ---------------------------------------------------------------------------------------
 // Operator preparation: T_raw[c][k][n] (FP64, paper basis, row k = image of unit solid k)
@@ -86,17 +87,15 @@ __global__ void k_shared_prep(const double *__restrict__ traw, int64_t nclass, i
 // The MFMAs are issued product by product over 20 independent accumulators.
 // ---------------------------------------------------------------------------------------
 template <int PREC>
-__global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
+__global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
 {
     constexpr int NPB = PREC == 6 ? 3 : 2;   // operator pieces
     constexpr int NPA = PREC == 6 ? 3 : 2;   // input pieces
-    constexpr int NPROD = PREC == 6 ? 6 : 3;
-    // products, smallest first: (input piece, operator piece)
-    constexpr int PA[6] = {PREC == 6 ? 2 : 1, PREC == 6 ? 1 : 0, 0, 1, 0, 0};
-    constexpr int PB[6] = {PREC == 6 ? 0 : 0, PREC == 6 ? 1 : 1, PREC == 6 ? 2 : 0, 0, 1, 0};
     __shared__ s16x8 Ap[NPA][kTM][kKC / 8 + 1];   // BF16 pieces, rows padded by one 16-byte slot
     __shared__ int tiles_before[kMaxClasses + 1];
+    __shared__ unsigned char live[kMaxK];
     const int tid = threadIdx.x, lane = tid & 63;
+    for (int k = tid; k < a.Kp; k += 256) live[k] = a.live_in[k];
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nclass = a.nclass;
     const int64_t count = a.count;
@@ -126,7 +125,12 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
     __syncthreads();
     const int total = tiles_before[nclass];
 
-    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    // XCD-aware walk: workgroups are dealt to the 8 XCDs in turn (blockIdx % 8), and each
+    // XCD takes a contiguous eighth of the work items, so that the few classes it works on at
+    // a time keep their operators in its own L2 (the grid is a multiple of 8)
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
+    const int w_end = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    for (int w = (int)(((int64_t)total * xcd) >> 3) + slot; w < w_end; w += per_xcd) {
         int lo = 0, hi = nclass - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -142,13 +146,15 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
         const int rows = (int)((s1 - first) < kTM ? (s1 - first) : kTM);
         const int nt0 = chunk * kNTC;
         // this wave's output tiles (tiles past the end re-read the last one; not stored)
-        const unsigned short *bptr[kNTW];
+        const unsigned short *bbase = a.frag + (int64_t)c * NPB * a.frag_class_stride + lane * 8;
+        int toff[kNTW];  // wave-uniform offsets of this wave's output tiles
 #pragma unroll
         for (int i = 0; i < kNTW; ++i) {
             const int nt = nt0 + wave + 4 * i;
             const int ntc = nt < a.NT ? nt : a.NT - 1;
-            bptr[i] = a.frag + (int64_t)c * NPB * a.frag_class_stride + (int64_t)ntc * a.KS * 512 + lane * 8;
+            toff[i] = __builtin_amdgcn_readfirstlane(ntc * a.KS * 512);
         }
+        const bool last_tile = nt0 + wave + 4 * (kNTW - 1) < a.NT;
 
         f32x4 acc[4][kNTW];
 #pragma unroll
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
         for (int i = 0; i < kNTW; ++i)
 #pragma unroll
             for (int q = 0; q < NPB; ++q)
-                bcur[i][q] = *reinterpret_cast<const s16x8 *>(bptr[i] + q * a.frag_class_stride);
+                bcur[i][q] = *reinterpret_cast<const s16x8 *>(bbase + toff[i] + q * a.frag_class_stride);
 
         for (int kc = 0; kc < a.Kp; kc += kKC) {
             const int kw = (a.Kp - kc) < kKC ? (a.Kp - kc) : kKC;  // multiple of 32
@@ -179,18 +185,18 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
                 for (int j = 0; j < 8; j += 2) {
                     float2 v = make_float2(0.f, 0.f);
                     if (k + j < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k + j);
-                    x[j] = a.live_in[k + j] ? v.x : 0.f;
-                    x[j + 1] = a.live_in[k + j + 1] ? v.y : 0.f;
+                    x[j] = live[k + j] ? v.x : 0.f;
+                    x[j + 1] = live[k + j + 1] ? v.y : 0.f;
                 }
                 s16x8 h, m, l;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const unsigned short hb = bf16_bits(x[j]);
-                    const float r1 = x[j] - bf16_value(hb);
-                    const unsigned short mb = bf16_bits(r1);
-                    h[j] = (short)hb;
-                    m[j] = (short)mb;
-                    l[j] = (short)bf16_bits(r1 - bf16_value(mb));
+                    const __bf16 hb = (__bf16)x[j];  // v_cvt_pk_bf16_f32: round to nearest even
+                    const float r1 = x[j] - (float)hb;
+                    const __bf16 mb = (__bf16)r1;
+                    h[j] = __builtin_bit_cast(short, hb);
+                    m[j] = __builtin_bit_cast(short, mb);
+                    if (NPA == 3) l[j] = __builtin_bit_cast(short, (__bf16)(r1 - (float)mb));
                 }
                 Ap[0][t][k8] = h;
                 Ap[1][t][k8] = m;
@@ -199,34 +205,55 @@ __global__ __launch_bounds__(256, 1) void k_shared_gemm(SharedArgs a)
             __syncthreads();
             for (int ks = 0; ks < kw / 32; ++ks) {
                 const int kglob = (kc >> 5) + ks;
-                // next K step's operator fragments, in flight during this step's MFMAs
                 const int knext = kglob + 1 < a.KS ? kglob + 1 : kglob;
-                s16x8 bnext[kNTW][NPB];
+                // input fragments: row 16 mt + lane % 16, k = 32 ks + 8 (lane / 16) + j; the high
+                // piece stays in registers for the step, the others pass through one slot
+                auto load_a = [&](int q, s16x8 (&f)[4]) {
 #pragma unroll
-                for (int i = 0; i < kNTW; ++i)
-#pragma unroll
-                    for (int q = 0; q < NPB; ++q)
-                        bnext[i][q] = *reinterpret_cast<const s16x8 *>(bptr[i] + q * a.frag_class_stride +
-                                                                       (int64_t)knext * 512);
-                // input fragments: row 16 mt + lane % 16, k = 32 ks + 8 (lane / 16) + j
-                s16x8 af[NPA][4];
-#pragma unroll
-                for (int q = 0; q < NPA; ++q)
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt) af[q][mt] = Ap[q][mt * 16 + (lane & 15)][4 * ks + (lane >> 4)];
-#pragma unroll
-                for (int pr = 0; pr < NPROD; ++pr)
+                    for (int mt = 0; mt < 4; ++mt) f[mt] = Ap[q][mt * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+                };
+                s16x8 ahi[4], ax[4];
+                load_a(0, ahi);
+                load_a(1, ax);
+                // one product (input fragments f x operator piece pb) over the 4 x 5 output blocks
+                auto mma = [&](const s16x8 (&f)[4], int pb) {
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                        for (int i = 0; i < kNTW; ++i)
+                        for (int i = 0; i < kNTW - 1; ++i)
                             acc[mt][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf16x8, af[PA[pr]][mt]), __builtin_bit_cast(bf16x8, bcur[i][PB[pr]]),
+                                __builtin_bit_cast(bf16x8, f[mt]), __builtin_bit_cast(bf16x8, bcur[i][pb]),
                                 acc[mt][i], 0, 0, 0);
+                    if (last_tile) {  // wave-uniform: this wave's fifth output tile exists
 #pragma unroll
-                for (int i = 0; i < kNTW; ++i)
+                        for (int mt = 0; mt < 4; ++mt)
+                            acc[mt][kNTW - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, f[mt]), __builtin_bit_cast(bf16x8, bcur[kNTW - 1][pb]),
+                                acc[mt][kNTW - 1], 0, 0, 0);
+                    }
+                };
+                // the next K step's operator piece q is loaded right after its last use here, so
+                // the loads fly during the remaining products
+                auto fetch = [&](int q) {
 #pragma unroll
-                    for (int q = 0; q < NPB; ++q) bcur[i][q] = bnext[i][q];
+                    for (int i = 0; i < kNTW; ++i)
+                        bcur[i][q] = *reinterpret_cast<const s16x8 *>(bbase + toff[i] + q * a.frag_class_stride +
+                                                                      knext * 512);
+                };
+                if (PREC == 6) {
+                    mma(ahi, 2);  // a_hi b_lo
+                    fetch(2);
+                }
+                mma(ahi, 1);      // a_hi b_mid
+                mma(ahi, 0);      // a_hi b_hi
+                if (PREC == 6) mma(ax, 1);  // a_mid b_mid
+                fetch(1);
+                mma(ax, 0);       // a_mid b_hi
+                if (PREC == 6) {
+                    load_a(2, ax);
+                    mma(ax, 0);   // a_lo b_hi
+                }
+                fetch(0);
             }
         }
         // store: D row (translation) 16 mt + 4 (lane / 16) + j, column (output) 16 nt + lane % 16
@@ -276,7 +303,9 @@ hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s)
     // enough work items for the whole batch, capped at the resident count (persistent loop)
     const int nchunks = (a.NT + kNTC - 1) / kNTC;
     const int64_t upper = ((a.count + kTM - 1) / kTM + a.nclass) * nchunks;
-    const dim3 grid((unsigned)(upper < res ? upper : res)), block(256);
+    int64_t g = upper < res ? upper : res;
+    g = (g + 7) / 8 * 8;  // a multiple of the XCD count (the kernel's walk assumes it)
+    const dim3 grid((unsigned)g), block(256);
     if (prec == 6)
         hipLaunchKernelGGL(k_shared_gemm<6>, grid, block, 0, s, a);
     else
