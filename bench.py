@@ -197,6 +197,66 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     return res
 
 
+def run_serving(sh, ctx, torch, dev, seconds=5.0, rate=200.0, n_slots=200_000):
+    """The serving workload: a Poisson stream (mean `rate` jobs/s, for `seconds`) of jobs of
+    10^3..10^5 translations (log-uniform), one order P in {4, 8, 16, 24, 30} and one dtype
+    (FP32 or FP64) per job, on resident trees (one per order and dtype, n_slots multipoles and
+    locals each).  Operations M2M / M2L / L2L with probabilities 0.2 / 0.6 / 0.2; M2M and L2L
+    read the first half of a pool and write the second.  Latency: submission to completion."""
+    from paper_2202_02847_amd import workloads as wl
+
+    orders = [4, 8, 16, 24, 30]
+    dts = [sh.SH_F64, sh.SH_F32]
+    pool = sum(2 * n_slots * P * (P + 1) * (8 if dt == sh.SH_F64 else 4) for P in orders for dt in dts)
+    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=512 << 20, streams=4, max_batch_jobs=64)
+    trees = {}
+    for P in orders:
+        for dt in dts:
+            t = srv.tree_create(dt, P, n_slots, P, n_slots)
+            npdt = np.float64 if dt == sh.SH_F64 else np.float32
+            block = np.random.default_rng(P).normal(size=(1000, P * (P + 1))).astype(npdt) * 1e-2
+            for pool_id in (0, 1):
+                for first in range(0, n_slots, 1000):
+                    srv.tree_write(t, pool_id, first, block)
+            trees[(P, dt)] = t
+    rng = wl.rng_for(5, 0)
+    ops = ["m2m", "m2l", "l2l"]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5)))
+    arrivals = arrivals[arrivals < seconds]
+    ids = []
+    log(f"[bench] serving {len(arrivals)} jobs over {seconds:.0f} s")
+    t0 = time.perf_counter()
+    for a in arrivals:
+        P = orders[rng.integers(len(orders))]
+        dt = dts[rng.integers(2)]
+        op = ops[rng.choice(3, p=[0.2, 0.6, 0.2])]
+        count = int(10 ** rng.uniform(3, 5))
+        r = wl.random_shifts(rng, count, 2.0, 6.0)
+        if op == "m2l":
+            src = rng.integers(0, n_slots, count)
+            dst = (rng.integers(n_slots) + np.arange(count)) % n_slots
+        else:
+            half = n_slots // 2
+            src = rng.integers(0, half, count)
+            dst = half + (rng.integers(half) + np.arange(count)) % half
+        delay = t0 + a - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(trees[(P, dt)], op, r, src, dst))
+    srv.drain()
+    for i in ids:
+        srv.wait(i)
+    st = srv.stats()
+    srv.close()
+    return {"jobs": st["jobs_done"], "failed": st["jobs_failed"], "offered_jobs_per_s": rate,
+            "duration_s": round(st["elapsed_s"], 3),
+            "translations_per_s": st["translations_done"] / max(st["elapsed_s"], 1e-9),
+            "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+            "max_ms": round(st["max_s"] * 1e3, 3), "mean_batch_jobs": round(st["mean_batch_jobs"], 2),
+            "batches": st["batches"], "queue_peak": st["queue_peak"],
+            "staging_peak_mb": round(st["staging_peak_bytes"] / 2 ** 20, 1)}
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -355,6 +415,9 @@ def main():
         t = time_launch(torch, lambda: sh.sh_m2l_naive_batch_f64(ctx, P, P, nv, d_r, d_M, S, d_L, S), 3)
         extra["m2l_p10_naive_f64_per_s"] = nv / t
         del d_M, d_L, d_M2, d_L2, I
+        torch.cuda.empty_cache()
+        log("[bench] serving")
+        extra["serving"] = run_serving(sh, ctx, torch, dev)
         torch.cuda.empty_cache()
         log("[bench] shared-direction precision forms P=16")
         extra["precision_p16"] = run_precision(sh, ctx, torch, dev)

@@ -236,6 +236,84 @@ int64_t sh_shared_bytes(const sh_shared *shared);
 /* Releases the operators.  NULL is accepted. */
 void sh_shared_destroy(sh_shared *shared);
 
+/* ---------------- serving: a request loop with continuous batching ----------------
+ * A server owns a device arena of resident expansion pools and a staging arena for the work
+ * records of jobs in flight, and runs a scheduler thread plus one completion thread per
+ * stream.  A "tree" is a pair of resident pools (multipoles of order p_m, locals of order
+ * p_l) that stay on the device between jobs.  A job is a batch of translations on one tree:
+ *   M2L: tree M pool slot src[i] -> L pool slot dst[i]  (orders p_m -> p_l);
+ *   M2M: M pool -> M pool;  L2L: L pool -> L pool;
+ * with shift r[3i..3i+2] (host arrays, copied at submission).  Destinations are unique within
+ * a job, and for M2M / L2L no destination is also a source.  Jobs are admitted by footprint
+ * (80 bytes of staging per translation plus 2 KiB) while the staging arena has room and
+ * their tree has no job in flight; every admissible job joins the next batch, which runs as
+ * one mixed work list per (dtype, accumulate) group on the least loaded stream, so batches
+ * overlap on the device.  A translation's result does not depend on the batch it ran in.
+ * Thread safety: every call may come from any host thread. */
+typedef struct sh_server sh_server;
+
+typedef struct sh_server_config {
+    int64_t pool_bytes;     /* device bytes for resident pools (trees) */
+    int64_t staging_bytes;  /* device bytes for jobs in flight: the admission budget (>= 64 KiB) */
+    int32_t streams;        /* concurrent streams, 1..8 */
+    int32_t max_batch_jobs; /* most jobs fused into one batch, >= 1 */
+} sh_server_config;
+
+typedef struct sh_job {
+    int32_t tree;         /* from sh_server_tree_create */
+    int32_t op;           /* SH_M2M, SH_M2L or SH_L2L */
+    int64_t count;        /* translations */
+    const double *r;      /* count x 3 shifts (host) */
+    const int64_t *src;   /* count source slots (host) */
+    const int64_t *dst;   /* count destination slots (host) */
+    uint32_t flags;       /* 0 or SH_ACCUMULATE */
+    uint32_t reserved;    /* 0 */
+} sh_job;
+
+typedef struct sh_server_stats {
+    int64_t jobs_done, jobs_failed, translations_done, batches, queue_peak;
+    int64_t staging_peak_bytes, pool_used_bytes;
+    double mean_batch_jobs;
+    double elapsed_s;       /* first submission to last completion */
+    double p50_s, p99_s, mean_s, max_s;  /* job latency: submission to completion */
+} sh_server_stats;
+
+/* Creates a server (allocates both arenas and pinned host staging, starts its threads).
+ * Errors: SH_EINVAL, SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_server_create(sh_ctx *ctx, const sh_server_config *config, sh_server **out);
+
+/* Finishes every submitted job, stops the threads and releases the server.  NULL is accepted. */
+void sh_server_destroy(sh_server *server);
+
+/* Carves a tree's pools (n_m solids of order p_m, n_l of order p_l, dtype SH_F64 or SH_F32;
+ * FP32 solids in the normalised basis) out of the pool arena.  Errors: SH_EINVAL, SH_EORDER,
+ * SH_EBUSY (no room in the arena). */
+sh_status sh_server_tree_create(sh_server *server, int dtype, int p_m, int64_t n_m, int p_l, int64_t n_l,
+                                int32_t *tree);
+
+/* Copies n solids starting at slot `first` of pool 0 (M) or 1 (L) from / to host memory,
+ * after the tree's queued and running jobs have finished (synchronous). */
+sh_status sh_server_tree_write(sh_server *server, int32_t tree, int pool, int64_t first, int64_t n,
+                               const void *host);
+sh_status sh_server_tree_read(sh_server *server, int32_t tree, int pool, int64_t first, int64_t n, void *host);
+
+/* Waits for the tree's jobs and returns its pools to the arena. */
+sh_status sh_server_tree_destroy(sh_server *server, int32_t tree);
+
+/* Queues a job (validated and copied; returns at once) and gives its id.  Errors: SH_EINVAL
+ * (unknown tree or op, a slot out of range, repeated destination, a destination that is
+ * also a source), SH_ESHIFT, SH_EBUSY (footprint above the whole staging arena). */
+sh_status sh_server_submit(sh_server *server, const sh_job *job, int64_t *job_id);
+
+/* Waits for a job, gives its latency in seconds and forgets it; returns its status. */
+sh_status sh_server_wait(sh_server *server, int64_t job_id, double *latency_s);
+
+/* Waits until no job is queued or running. */
+sh_status sh_server_drain(sh_server *server);
+
+/* Counters and latency percentiles since creation. */
+sh_status sh_server_stats_get(sh_server *server, sh_server_stats *stats);
+
 /* ---------------- single translation (host pointers, synchronous) ----------------
  * The paper's statement of the problem: one input solid, one shift, one output solid.
  * Errors: SH_EINVAL, SH_EORDER, SH_ESHIFT (M2L with r = 0 or non-finite r), SH_EDEVICE. */

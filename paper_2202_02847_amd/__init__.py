@@ -66,6 +66,16 @@ _SIGS = {
     "sh_shared_execute": (_c_i32, [_vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
     "sh_shared_bytes": (_c_i64, [_vp]),
     "sh_shared_destroy": (None, [_vp]),
+    "sh_server_create": (_c_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "sh_server_destroy": (None, [_vp]),
+    "sh_server_tree_create": (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _c_i32, _c_i64, ctypes.POINTER(ctypes.c_int32)]),
+    "sh_server_tree_write": (_c_i32, [_vp, ctypes.c_int32, _c_i32, _c_i64, _c_i64, _vp]),
+    "sh_server_tree_read": (_c_i32, [_vp, ctypes.c_int32, _c_i32, _c_i64, _c_i64, _vp]),
+    "sh_server_tree_destroy": (_c_i32, [_vp, ctypes.c_int32]),
+    "sh_server_submit": (_c_i32, [_vp, _vp, ctypes.POINTER(_c_i64)]),
+    "sh_server_wait": (_c_i32, [_vp, _c_i64, ctypes.POINTER(ctypes.c_double)]),
+    "sh_server_drain": (_c_i32, [_vp]),
+    "sh_server_stats_get": (_c_i32, [_vp, _vp]),
 }
 for _op in ("m2l", "m2m", "l2l"):
     for _dt in ("f64", "f32"):
@@ -396,3 +406,138 @@ def sh_shared_bytes(shared: Shared) -> int:
 
 def sh_shared_destroy(shared: Shared) -> None:
     shared.close()
+
+
+# ---------------- serving ----------------
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("staging_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("max_batch_jobs", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_int32), ("op", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("r", ctypes.c_void_p), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("jobs_done", "jobs_failed", "translations_done", "batches",
+                                              "queue_peak", "staging_peak_bytes", "pool_used_bytes")] + \
+               [(n, ctypes.c_double) for n in ("mean_batch_jobs", "elapsed_s", "p50_s", "p99_s", "mean_s", "max_s")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Server:
+    """Owning wrapper of an ``sh_server*`` (sh_server_create / sh_server_destroy)."""
+
+    def __init__(self, ctx, pool_bytes, staging_bytes=64 << 20, streams=2, max_batch_jobs=64):
+        cfg = ServerConfig(pool_bytes, staging_bytes, streams, max_batch_jobs)
+        h = _vp()
+        _check(lib().sh_server_create(_h(ctx), ctypes.byref(cfg), ctypes.byref(h)), "sh_server_create")
+        self._h = h.value
+        self.ctx = ctx
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("server destroyed")
+        return self._h
+
+    def tree_create(self, dtype, p_m, n_m, p_l, n_l) -> int:
+        t = ctypes.c_int32()
+        _check(lib().sh_server_tree_create(self.handle, dtype, p_m, n_m, p_l, n_l, ctypes.byref(t)),
+               "sh_server_tree_create")
+        return t.value
+
+    def tree_write(self, tree, pool, first, solids: np.ndarray):
+        a = np.ascontiguousarray(solids)
+        _check(lib().sh_server_tree_write(self.handle, tree, pool, first, a.shape[0], a.ctypes.data),
+               "sh_server_tree_write")
+
+    def tree_read(self, tree, pool, first, n, P, dtype=np.float64) -> np.ndarray:
+        out = np.zeros((n, P * (P + 1)), dtype)
+        _check(lib().sh_server_tree_read(self.handle, tree, pool, first, n, out.ctypes.data), "sh_server_tree_read")
+        return out
+
+    def tree_destroy(self, tree):
+        _check(lib().sh_server_tree_destroy(self.handle, tree), "sh_server_tree_destroy")
+
+    def submit(self, tree, op, r, src, dst, flags=0) -> int:
+        r = np.ascontiguousarray(np.reshape(r, (-1, 3)), dtype=np.float64)
+        src = np.ascontiguousarray(src, dtype=np.int64)
+        dst = np.ascontiguousarray(dst, dtype=np.int64)
+        n = len(src)
+        if r.shape[0] != n or len(dst) != n:
+            raise ValueError("r, src and dst must describe the same number of translations")
+        job = Job(tree, OPS.get(op, op), n, r.ctypes.data if n else None, src.ctypes.data if n else None,
+                  dst.ctypes.data if n else None, flags, 0)
+        jid = _c_i64()
+        _check(lib().sh_server_submit(self.handle, ctypes.byref(job), ctypes.byref(jid)), "sh_server_submit")
+        return jid.value
+
+    def wait(self, job_id) -> float:
+        lat = ctypes.c_double()
+        _check(lib().sh_server_wait(self.handle, job_id, ctypes.byref(lat)), "sh_server_wait")
+        return lat.value
+
+    def drain(self):
+        _check(lib().sh_server_drain(self.handle), "sh_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().sh_server_stats_get(self.handle, ctypes.byref(st)), "sh_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().sh_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sh_server_create(ctx, pool_bytes, staging_bytes=64 << 20, streams=2, max_batch_jobs=64) -> Server:
+    return Server(ctx, pool_bytes, staging_bytes, streams, max_batch_jobs)
+
+
+def sh_server_destroy(server: Server) -> None:
+    server.close()
+
+
+def sh_server_tree_create(server: Server, dtype, p_m, n_m, p_l, n_l) -> int:
+    return server.tree_create(dtype, p_m, n_m, p_l, n_l)
+
+
+def sh_server_tree_write(server: Server, tree, pool, first, solids) -> None:
+    server.tree_write(tree, pool, first, solids)
+
+
+def sh_server_tree_read(server: Server, tree, pool, first, n, P, dtype=np.float64) -> np.ndarray:
+    return server.tree_read(tree, pool, first, n, P, dtype)
+
+
+def sh_server_tree_destroy(server: Server, tree) -> None:
+    server.tree_destroy(tree)
+
+
+def sh_server_submit(server: Server, tree, op, r, src, dst, flags=0) -> int:
+    return server.submit(tree, op, r, src, dst, flags)
+
+
+def sh_server_wait(server: Server, job_id) -> float:
+    return server.wait(job_id)
+
+
+def sh_server_drain(server: Server) -> None:
+    server.drain()
+
+
+def sh_server_stats_get(server: Server) -> dict:
+    return server.stats()

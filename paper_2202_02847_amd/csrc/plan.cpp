@@ -26,11 +26,16 @@
 
 #include "context.hpp"
 #include "kernels.hpp"
+#include "list_plan.hpp"
 
 using shfmm::DeviceGuard;
 using shfmm::ListArgs;
 using shfmm::ListItem;
 using shfmm::ListTask;
+using shfmm::ListBin;
+using shfmm::MAP_GENERAL;
+using shfmm::MAP_LPT32;
+using shfmm::MAP_LPT64;
 
 static_assert(sizeof(sh_item) == sizeof(ListItem), "sh_item and ListItem must agree");
 static_assert(offsetof(sh_item, in_off) == offsetof(ListItem, in_off), "sh_item layout");
@@ -39,19 +44,7 @@ static_assert(offsetof(sh_item, r) == offsetof(ListItem, r), "sh_item layout");
 
 namespace {
 
-enum Mapping { MAP_LPT64 = 0, MAP_LPT32 = 1, MAP_GENERAL = 2 };
 const char *mapping_name(int m) { return m == MAP_LPT64 ? "lpt64" : m == MAP_LPT32 ? "lpt32" : "wave"; }
-
-struct Bin {
-    int mapping = MAP_LPT64;
-    int op = -1;       // lane-per-translation bins: the operation (general bins mix them)
-    int bucket = 0;    // order bucket (lane-per-translation) or order class (general)
-    bool wide = false; // FP32 I/O with FP64 arithmetic (orders >= 20)
-    int pmax = 0;      // largest order in the bin
-    bool tuned = false;
-    int64_t item_first = 0, item_count = 0;
-    int64_t task_first = 0, task_count = 0;
-};
 
 int64_t solid_reals(int p) { return (int64_t)p * (p + 1); }
 int64_t cost(const ListItem &it) { return (int64_t)it.p_in * it.p_in * it.p_in + (int64_t)it.p_out * it.p_out * it.p_out; }
@@ -128,7 +121,7 @@ void tune_store(const TuneKey &k, int m)
 // ---------------- layout of a set of bins on the device ----------------
 
 // Orders the items of one bin and, for lane-per-translation bins, cuts them into tasks.
-void lay_out_bin(Bin &b, std::vector<ListItem> &items, std::vector<ListTask> &tasks, int task_size)
+void lay_out_bin(ListBin &b, std::vector<ListItem> &items, std::vector<ListTask> &tasks, int task_size)
 {
     auto first = items.begin() + b.item_first, last = first + b.item_count;
     std::stable_sort(first, last, [](const ListItem &a, const ListItem &c) {
@@ -157,8 +150,10 @@ void lay_out_bin(Bin &b, std::vector<ListItem> &items, std::vector<ListTask> &ta
     b.task_count = (int64_t)tasks.size() - b.task_first;
 }
 
-hipError_t launch_bin(const sh_ctx *ctx, bool f32, const Bin &b, const ListItem *d_items, const ListTask *d_tasks,
-                      const void *in, void *out, unsigned flags, hipStream_t s)
+}  // namespace
+
+hipError_t shfmm::launch_list_bin(const sh_ctx *ctx, bool f32, const ListBin &b, const ListItem *d_items,
+                                  const ListTask *d_tasks, const void *in, void *out, unsigned flags, hipStream_t s)
 {
     ListArgs la{};
     la.items = d_items + b.item_first;
@@ -172,6 +167,8 @@ hipError_t launch_bin(const sh_ctx *ctx, bool f32, const Bin &b, const ListItem 
     if (b.mapping == MAP_GENERAL) return shfmm::launch_list_general(ctx->tabs, la, f32, b.wide, b.pmax, s);
     return shfmm::launch_list_lpt(ctx->tabs, la, b.op, f32, b.bucket, s);
 }
+
+namespace {
 
 // Device copy of a laid-out item / task set: one allocation, items first.
 struct DeviceLists {
@@ -197,7 +194,7 @@ struct DeviceLists {
 
 // Times one mapping of a lane-per-translation bin on a sample of its items (offsets
 // remapped densely into zero-filled scratch arenas).  Returns milliseconds, or < 0 on error.
-float time_mapping(const sh_ctx *ctx, bool f32, const Bin &proto, const std::vector<ListItem> &sample, int mapping,
+float time_mapping(const sh_ctx *ctx, bool f32, const ListBin &proto, const std::vector<ListItem> &sample, int mapping,
                    unsigned flags, hipStream_t s)
 {
     std::vector<ListItem> it(sample);
@@ -208,7 +205,7 @@ float time_mapping(const sh_ctx *ctx, bool f32, const Bin &proto, const std::vec
         in_total += solid_reals(x.p_in);
         out_total += solid_reals(x.p_out);
     }
-    Bin b = proto;
+    ListBin b = proto;
     b.mapping = mapping;
     b.item_first = 0;
     b.item_count = (int64_t)it.size();
@@ -225,10 +222,10 @@ float time_mapping(const sh_ctx *ctx, bool f32, const Bin &proto, const std::vec
     if (hipMemsetAsync(arena, 0, ab, s) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
         hipEventCreate(&e1) == hipSuccess) {
         void *ain = arena, *aout = reinterpret_cast<char *>(arena) + (size_t)in_total * elem;
-        bool ok = launch_bin(ctx, f32, b, dl.items, dl.tasks, ain, aout, flags, s) == hipSuccess;
+        bool ok = shfmm::launch_list_bin(ctx, f32, b, dl.items, dl.tasks, ain, aout, flags, s) == hipSuccess;
         for (int rep = 0; ok && rep < 3; ++rep) {
             ok = hipEventRecord(e0, s) == hipSuccess &&
-                 launch_bin(ctx, f32, b, dl.items, dl.tasks, ain, aout, flags, s) == hipSuccess &&
+                 shfmm::launch_list_bin(ctx, f32, b, dl.items, dl.tasks, ain, aout, flags, s) == hipSuccess &&
                  hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0;
             if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best < 0 || ms < best)) best = ms;
@@ -284,7 +281,7 @@ struct sh_plan {
     unsigned flags = 0;
     int64_t count = 0;
     int64_t in_extent = 0, out_extent = 0;  // reals the arenas must hold
-    std::vector<Bin> bins;
+    std::vector<ListBin> bins;
     DeviceLists dev;
     std::vector<std::pair<int64_t, int64_t>> outs;  // output intervals, sorted
     std::vector<std::pair<int64_t, int64_t>> ins;   // merged input intervals
@@ -342,74 +339,38 @@ sh_status plan_build(sh_ctx *ctx, int dtype, const sh_item *items, int64_t count
     if (!disjoint_sorted(p->outs)) return SH_EINVAL;
     p->ins = merged(std::move(ins));
 
-    // group: lane-per-translation candidates by (op, bucket); the rest by (class, width)
-    std::map<std::tuple<int, int, int, int>, std::vector<ListItem>> groups;  // (mapping kind, op, bucket, wide)
-    for (const ListItem &it : list) {
-        const int pm = std::max(it.p_in, it.p_out);
-        const int bk = lpt_bucket(pm);
-        if (bk > 0)
-            groups[std::make_tuple(0, it.op, bk, 0)].push_back(it);
-        else {
-            const bool wide = f32 && pm >= shfmm::kF32WideOrder;
-            groups[std::make_tuple(1, -1, general_class(pm), wide ? 1 : 0)].push_back(it);
-        }
-    }
-    list.clear();
     hipStream_t ts = nullptr;
     if ((flags & SH_PLAN_AUTOTUNE) && hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess)
         return SH_EDEVICE;
-    std::vector<ListTask> tasks;
-    sh_status st = SH_OK;
-    for (auto &g : groups) {
-        auto &v = g.second;
-        Bin b;
-        b.op = std::get<1>(g.first);
-        b.bucket = std::get<2>(g.first);
-        b.wide = std::get<3>(g.first) != 0;
-        for (auto &x : v) b.pmax = std::max(b.pmax, std::max(x.p_in, x.p_out));
-        if (std::get<0>(g.first) == 1) {
-            b.mapping = MAP_GENERAL;
-        } else {
-            const TuneKey key{dtype, b.op, b.bucket, count_class((int64_t)v.size())};
-            int m = MAP_LPT64;
-            if (tune_lookup(key, &m)) {
-                b.tuned = true;
-            } else if (flags & SH_PLAN_AUTOTUNE) {
-                // a strided sample keeps the mix of orders of the bin
-                const size_t kSample = 1 << 15;
-                std::vector<ListItem> sample;
-                const size_t stride = v.size() > kSample ? (v.size() + kSample - 1) / kSample : 1;
-                for (size_t i = 0; i < v.size(); i += stride) sample.push_back(v[i]);
-                float best = -1;
-                for (int cand : {MAP_LPT64, MAP_LPT32, MAP_GENERAL}) {
-                    const float ms = time_mapping(ctx, f32, b, sample, cand, flags, ts);
-                    if (ms < 0) { st = SH_EDEVICE; break; }
-                    if (best < 0 || ms < best) { best = ms; m = cand; }
-                }
-                if (st != SH_OK) break;
-                tune_store(key, m);
-                b.tuned = true;
-            }
-            b.mapping = m;
+    auto choose = [&](ListBin &b, const std::vector<ListItem> &v) -> int {
+        bool tuned = false;
+        int m = shfmm::cached_mapping(dtype, b.op, b.bucket, (int64_t)v.size(), &tuned);
+        if (tuned || !(flags & SH_PLAN_AUTOTUNE)) {
+            b.tuned = tuned;
+            return m;
         }
-        b.item_first = (int64_t)list.size();
-        b.item_count = (int64_t)v.size();
-        list.insert(list.end(), v.begin(), v.end());
-        std::vector<ListItem>().swap(v);
-        lay_out_bin(b, list, tasks, b.mapping == MAP_LPT32 ? 32 : 64);
-        p->bins.push_back(b);
-    }
+        // a strided sample keeps the mix of orders of the bin
+        const size_t kSample = 1 << 15;
+        std::vector<ListItem> sample;
+        const size_t stride = v.size() > kSample ? (v.size() + kSample - 1) / kSample : 1;
+        for (size_t i = 0; i < v.size(); i += stride) sample.push_back(v[i]);
+        float best = -1;
+        for (int cand : {MAP_LPT64, MAP_LPT32, MAP_GENERAL}) {
+            const float ms = time_mapping(ctx, f32, b, sample, cand, flags, ts);
+            if (ms < 0) return -1;
+            if (best < 0 || ms < best) {
+                best = ms;
+                m = cand;
+            }
+        }
+        tune_store(TuneKey{dtype, b.op, b.bucket, count_class((int64_t)v.size())}, m);
+        b.tuned = true;
+        return m;
+    };
+    std::vector<ListTask> tasks;
+    const sh_status st = shfmm::bin_items(dtype, list, tasks, p->bins, choose);
     if (ts) (void)hipStreamDestroy(ts);
     if (st != SH_OK) return st;
-    // largest bins first, so that their persistent grids start first on the device
-    std::vector<size_t> order(p->bins.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-        return p->bins[a].item_count * p->bins[a].pmax > p->bins[b].item_count * p->bins[b].pmax;
-    });
-    std::vector<Bin> sorted;
-    for (size_t i : order) sorted.push_back(p->bins[i]);
-    p->bins.swap(sorted);
     const hipError_t e = p->dev.upload(list, tasks);
     if (e == hipErrorOutOfMemory) return SH_ENOMEM;
     return e == hipSuccess ? SH_OK : SH_EDEVICE;
@@ -440,7 +401,7 @@ hipError_t capture(sh_plan *p, const void *in, void *out)
     hipError_t le = hipEventRecord(p->fork, p->cap);
     for (size_t i = 0; le == hipSuccess && i < nside; ++i) le = hipStreamWaitEvent(p->side[i], p->fork, 0);
     for (size_t i = 0; le == hipSuccess && i < p->bins.size(); ++i)
-        le = launch_bin(p->ctx, f32, p->bins[i], p->dev.items, p->dev.tasks, in, out, p->flags, p->side[i % nside]);
+        le = shfmm::launch_list_bin(p->ctx, f32, p->bins[i], p->dev.items, p->dev.tasks, in, out, p->flags, p->side[i % nside]);
     for (size_t i = 0; le == hipSuccess && i < nside; ++i) {
         le = hipEventRecord(p->join[i], p->side[i]);
         if (le == hipSuccess) le = hipStreamWaitEvent(p->cap, p->join[i], 0);
@@ -484,8 +445,8 @@ sh_status plan_execute(sh_plan *p, const void *in, int64_t in_reals, void *out, 
     const bool f32 = p->dtype == SH_F32;
     if (!p->done && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) return SH_EDEVICE;
     if (p->flags & SH_PLAN_NO_GRAPH) {
-        for (const Bin &b : p->bins)
-            if (launch_bin(p->ctx, f32, b, p->dev.items, p->dev.tasks, in, out, p->flags, s) != hipSuccess)
+        for (const ListBin &b : p->bins)
+            if (shfmm::launch_list_bin(p->ctx, f32, b, p->dev.items, p->dev.tasks, in, out, p->flags, s) != hipSuccess)
                 return SH_EDEVICE;
     } else {
         if (!p->exec || p->g_in != in || p->g_out != out) {
@@ -507,7 +468,7 @@ std::string describe(const sh_plan *p)
     s += ", \"bins\": [";
     static const char *ops[] = {"m2m", "m2l", "l2l"};
     for (size_t i = 0; i < p->bins.size(); ++i) {
-        const Bin &b = p->bins[i];
+        const ListBin &b = p->bins[i];
         if (i) s += ", ";
         s += "{\"mapping\": \"";
         s += mapping_name(b.mapping);
@@ -526,6 +487,61 @@ std::string describe(const sh_plan *p)
 }
 
 }  // namespace
+
+sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<ListTask> &tasks,
+                           std::vector<ListBin> &bins, const MappingChoice &choose)
+{
+    const bool f32 = dtype == SH_F32;
+    // group: lane-per-translation candidates by (op, bucket); the rest by (class, width)
+    std::map<std::tuple<int, int, int, int>, std::vector<ListItem>> groups;  // (kind, op, bucket, wide)
+    for (const ListItem &it : list) {
+        const int pm = std::max(it.p_in, it.p_out);
+        const int bk = lpt_bucket(pm);
+        if (bk > 0)
+            groups[std::make_tuple(0, it.op, bk, 0)].push_back(it);
+        else {
+            const bool wide = f32 && pm >= shfmm::kF32WideOrder;
+            groups[std::make_tuple(1, -1, general_class(pm), wide ? 1 : 0)].push_back(it);
+        }
+    }
+    list.clear();
+    std::vector<ListBin> made;
+    for (auto &g : groups) {
+        auto &v = g.second;
+        ListBin b;
+        b.op = std::get<1>(g.first);
+        b.bucket = std::get<2>(g.first);
+        b.wide = std::get<3>(g.first) != 0;
+        for (auto &x : v) b.pmax = std::max(b.pmax, std::max(x.p_in, x.p_out));
+        if (std::get<0>(g.first) == 1) {
+            b.mapping = MAP_GENERAL;
+        } else {
+            const int m = choose(b, v);
+            if (m < 0) return SH_EDEVICE;
+            b.mapping = m;
+        }
+        b.item_first = (int64_t)list.size();
+        b.item_count = (int64_t)v.size();
+        list.insert(list.end(), v.begin(), v.end());
+        std::vector<ListItem>().swap(v);
+        lay_out_bin(b, list, tasks, b.mapping == MAP_LPT32 ? 32 : 64);
+        made.push_back(b);
+    }
+    // largest bins first, so that their persistent grids start first on the device
+    std::stable_sort(made.begin(), made.end(), [](const ListBin &a, const ListBin &b) {
+        return a.item_count * a.pmax > b.item_count * b.pmax;
+    });
+    bins.insert(bins.end(), made.begin(), made.end());
+    return SH_OK;
+}
+
+int shfmm::cached_mapping(int dtype, int op, int bucket, int64_t count, bool *tuned)
+{
+    int m = MAP_LPT64;
+    const bool hit = tune_lookup(TuneKey{dtype, op, bucket, count_class(count)}, &m);
+    if (tuned) *tuned = hit;
+    return hit ? m : MAP_LPT64;
+}
 
 extern "C" {
 

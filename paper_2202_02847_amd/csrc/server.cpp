@@ -1,0 +1,695 @@
+// Serving runtime: a request loop for translation jobs with continuous batching.
+//
+// * Resident pools.  A "tree" owns a multipole pool and a local pool (solids of one order
+//   each) carved out of one device arena, and keeps them between jobs.
+// * Admission by HBM footprint.  A job's footprint is the device staging its work records
+//   take while it is in flight (an upper bound of 80 bytes per translation plus 2 KiB);
+//   jobs are admitted, first come first served with backfill, while the staging arena has
+//   room and their tree has no job in flight.
+// * Continuous batching.  The scheduler thread fuses every admissible job into one batch:
+//   one mixed work list per (dtype, accumulate) group, binned and launched like a plan, on
+//   the least loaded of a few streams, so batches overlap on the device and jobs arriving
+//   meanwhile join the next batch as soon as staging frees up.
+// * Latency.  One completion thread per stream waits for its batches in order and stamps
+//   every job of a finished batch; p50 / p99 are taken over all completed jobs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "context.hpp"
+#include "kernels.hpp"
+#include "list_plan.hpp"
+
+using shfmm::DeviceGuard;
+using shfmm::ListBin;
+using shfmm::ListItem;
+using shfmm::ListTask;
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int64_t kAlign = 256;
+int64_t round_up(int64_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit range allocator over [0, size) with coalescing, 256-byte granules.
+struct RangeAlloc {
+    std::map<int64_t, int64_t> free_;  // offset -> length
+    int64_t size = 0, used = 0, peak = 0;
+    void init(int64_t s)
+    {
+        size = s;
+        free_.clear();
+        if (s > 0) free_[0] = s;
+    }
+    int64_t alloc(int64_t n)
+    {
+        n = round_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const int64_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[off + n] = len - n;
+            used += n;
+            peak = std::max(peak, used);
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n)
+    {
+        n = round_up(n);
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Tree {
+    int dtype = SH_F64;
+    int p_m = 0, p_l = 0;
+    int64_t n_m = 0, n_l = 0;
+    int64_t off_m = 0, off_l = 0;  // byte offsets in the pool arena
+    int64_t bytes_m = 0, bytes_l = 0;
+    bool busy = false;             // a job on this tree is in flight
+    int pending = 0;               // jobs queued or in flight
+};
+
+struct Job {
+    int32_t tree = 0, op = 0;
+    unsigned flags = 0;
+    std::vector<double> r;
+    std::vector<int64_t> src, dst;
+    int64_t footprint = 0;
+    double t_submit = 0, t_done = 0;
+    bool done = false;
+    int status = SH_OK;
+};
+
+struct Batch {
+    int stream = 0;
+    hipEvent_t ev = nullptr;
+    std::vector<int64_t> jobs;
+    std::vector<Job *> jp;          // the jobs (stable: owned by unique_ptr)
+    std::vector<const Tree *> tp;   // their trees (stable: map nodes, kept while jobs pend)
+    int64_t st_off = -1, st_bytes = 0;
+    int64_t translations = 0;
+    bool launched = true;
+};
+
+int64_t job_footprint(int64_t count) { return 80 * count + 2048; }
+
+}  // namespace
+
+struct sh_server {
+    sh_ctx *ctx = nullptr;
+    sh_server_config cfg{};
+    void *pool = nullptr;        // device arena of resident pools
+    void *dstage = nullptr;      // device staging (work records)
+    void *hstage = nullptr;      // pinned host staging, same offsets
+    RangeAlloc pool_alloc, stage_alloc;
+    std::vector<hipStream_t> streams;
+    std::vector<std::deque<Batch>> inflight;
+    std::vector<std::thread> completers;
+    std::thread scheduler;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done, cv_complete;
+    std::deque<int64_t> queue;
+    std::unordered_map<int64_t, std::unique_ptr<Job>> jobs;
+    std::map<int32_t, Tree> trees;
+    int32_t next_tree = 1;
+    int64_t next_job = 1;
+    bool stop = false;
+    bool sched_done = false;
+    // statistics
+    std::vector<double> latencies;
+    int64_t jobs_done = 0, translations_done = 0, batches = 0, batch_jobs = 0, queue_peak = 0, failed = 0;
+    double t_first_submit = -1, t_last_done = -1;
+
+    int inflight_total() const
+    {
+        int n = 0;
+        for (auto &d : inflight) n += (int)d.size();
+        return n;
+    }
+};
+
+namespace {
+
+// Appends one job's work records to the per-(dtype, accumulate) lists.
+void job_items(const Tree &t, const Job &j, std::vector<ListItem> &out)
+{
+    const int64_t elem = t.dtype == SH_F32 ? 4 : 8;
+    const int64_t sm = (int64_t)t.p_m * (t.p_m + 1), sl = (int64_t)t.p_l * (t.p_l + 1);
+    int64_t in_base, out_base, s_in, s_out;
+    int p_in, p_out;
+    if (j.op == SH_M2L) {
+        in_base = t.off_m / elem; s_in = sm; p_in = t.p_m;
+        out_base = t.off_l / elem; s_out = sl; p_out = t.p_l;
+    } else if (j.op == SH_M2M) {
+        in_base = out_base = t.off_m / elem; s_in = s_out = sm; p_in = p_out = t.p_m;
+    } else {
+        in_base = out_base = t.off_l / elem; s_in = s_out = sl; p_in = p_out = t.p_l;
+    }
+    const size_t n = j.src.size();
+    for (size_t i = 0; i < n; ++i) {
+        ListItem it{};
+        it.op = j.op;
+        it.p_in = p_in;
+        it.p_out = p_out;
+        it.in_off = in_base + j.src[i] * s_in;
+        it.out_off = out_base + j.dst[i] * s_out;
+        it.r[0] = j.r[3 * i];
+        it.r[1] = j.r[3 * i + 1];
+        it.r[2] = j.r[3 * i + 2];
+        out.push_back(it);
+    }
+}
+
+// Builds and launches one batch (called by the scheduler without the lock; the batch's jobs
+// and trees are reserved, so nothing it reads changes meanwhile).
+hipError_t launch_batch(sh_server *S, Batch &b)
+{
+    // groups: (dtype, accumulate)
+    std::vector<ListItem> items[2][2];
+    for (size_t k = 0; k < b.jp.size(); ++k) {
+        const Job &j = *b.jp[k];
+        const int dt = b.tp[k]->dtype;
+        job_items(*b.tp[k], j, items[dt][(j.flags & SH_ACCUMULATE) ? 1 : 0]);
+    }
+    struct Group {
+        int dtype;
+        unsigned flags;
+        std::vector<ListItem> items;
+        std::vector<ListTask> tasks;
+        std::vector<ListBin> bins;
+        int64_t item_off = 0, task_off = 0;
+    };
+    std::vector<Group> groups;
+    int64_t bytes = 0;
+    for (int dt = 0; dt < 2; ++dt)
+        for (int acc = 0; acc < 2; ++acc) {
+            if (items[dt][acc].empty()) continue;
+            Group g;
+            g.dtype = dt;
+            g.flags = acc ? SH_ACCUMULATE : 0;
+            g.items.swap(items[dt][acc]);
+            // a fixed mapping: the kernel a translation runs on follows from its own operation
+            // and orders, never from the other jobs of the batch
+            auto choose = [](ListBin &, const std::vector<ListItem> &) { return (int)shfmm::MAP_LPT64; };
+            if (shfmm::bin_items(dt, g.items, g.tasks, g.bins, choose) != SH_OK) return hipErrorUnknown;
+            g.item_off = bytes;
+            bytes = round_up(bytes + (int64_t)(g.items.size() * sizeof(ListItem)));
+            g.task_off = bytes;
+            bytes = round_up(bytes + (int64_t)(g.tasks.size() * sizeof(ListTask)));
+            groups.push_back(std::move(g));
+        }
+    if (bytes > b.st_bytes) return hipErrorInvalidValue;  // footprint bound violated (cannot happen)
+    char *h = static_cast<char *>(S->hstage) + b.st_off;
+    char *d = static_cast<char *>(S->dstage) + b.st_off;
+    for (auto &g : groups) {
+        std::memcpy(h + g.item_off, g.items.data(), g.items.size() * sizeof(ListItem));
+        if (!g.tasks.empty()) std::memcpy(h + g.task_off, g.tasks.data(), g.tasks.size() * sizeof(ListTask));
+    }
+    hipStream_t s = S->streams[b.stream];
+    hipError_t e = hipMemcpyAsync(d, h, (size_t)bytes, hipMemcpyHostToDevice, s);
+    for (auto &g : groups) {
+        const bool f32 = g.dtype == SH_F32;
+        const ListItem *di = reinterpret_cast<const ListItem *>(d + g.item_off);
+        const ListTask *dtk = reinterpret_cast<const ListTask *>(d + g.task_off);
+        for (const ListBin &bin : g.bins) {
+            if (e != hipSuccess) break;
+            e = shfmm::launch_list_bin(S->ctx, f32, bin, di, dtk, S->pool, S->pool, g.flags, s);
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(b.ev, s);
+    return e;
+}
+
+void scheduler_main(sh_server *S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        // gather a batch: every queued job (first come first served, later ones backfill)
+        // whose tree is idle and whose footprint fits the staging left
+        Batch b;
+        int stream = -1;
+        size_t best = SIZE_MAX;
+        for (size_t i = 0; i < S->inflight.size(); ++i)
+            if (S->inflight[i].size() < 2 && S->inflight[i].size() < best) {
+                best = S->inflight[i].size();
+                stream = (int)i;
+            }
+        if (stream >= 0 && !S->queue.empty()) {
+            int64_t need = 0;
+            std::vector<size_t> take;
+            std::vector<int32_t> claimed;
+            const int64_t free_total = S->stage_alloc.size - S->stage_alloc.used;
+            for (size_t qi = 0; qi < S->queue.size() && (int)take.size() < S->cfg.max_batch_jobs; ++qi) {
+                const Job &j = *S->jobs.at(S->queue[qi]);
+                Tree &t = S->trees.at(j.tree);
+                if (t.busy || std::find(claimed.begin(), claimed.end(), j.tree) != claimed.end()) continue;
+                if (need + j.footprint > free_total) continue;
+                need += j.footprint;
+                take.push_back(qi);
+                claimed.push_back(j.tree);
+            }
+            if (!take.empty()) {
+                int64_t off = S->stage_alloc.alloc(need);
+                while (off < 0 && take.size() > 1) {  // fragmentation: shrink the batch
+                    need -= S->jobs.at(S->queue[take.back()])->footprint;
+                    take.pop_back();
+                    claimed.pop_back();
+                    off = S->stage_alloc.alloc(need);
+                }
+                if (off >= 0) {
+                    b.stream = stream;
+                    b.st_off = off;
+                    b.st_bytes = round_up(need);
+                    for (size_t k = take.size(); k-- > 0;) {
+                        const int64_t id = S->queue[take[k]];
+                        b.jobs.push_back(id);
+                        S->queue.erase(S->queue.begin() + (std::ptrdiff_t)take[k]);
+                    }
+                    std::reverse(b.jobs.begin(), b.jobs.end());
+                    for (int64_t id : b.jobs) {
+                        Job *j = S->jobs.at(id).get();
+                        Tree &t = S->trees.at(j->tree);
+                        t.busy = true;
+                        b.jp.push_back(j);
+                        b.tp.push_back(&t);
+                        b.translations += (int64_t)j->src.size();
+                    }
+                }
+            }
+        }
+        if (b.jobs.empty()) {
+            if (S->stop && S->queue.empty()) break;
+            S->cv_sched.wait(lk);
+            continue;
+        }
+        // jobs, trees and staging of the batch are reserved: nothing launch_batch reads is
+        // changed by other threads until the batch completes
+        // launch outside the lock
+        lk.unlock();
+        hipError_t e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = launch_batch(S, b);
+        lk.lock();
+        b.launched = e == hipSuccess;
+        if (!b.launched)
+            for (Job *j : b.jp) j->status = SH_EDEVICE;
+        ++S->batches;
+        S->batch_jobs += (int64_t)b.jobs.size();
+        S->inflight[b.stream].push_back(std::move(b));
+        S->cv_complete.notify_all();
+    }
+    S->sched_done = true;
+    S->cv_complete.notify_all();
+}
+
+void completer_main(sh_server *S, int stream)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_complete.wait(lk, [&] { return !S->inflight[stream].empty() || S->sched_done; });
+        if (S->inflight[stream].empty()) break;  // the scheduler has finished and nothing is left
+        Batch &b = S->inflight[stream].front();
+        const hipEvent_t ev = b.ev;
+        const bool launched = b.launched;
+        lk.unlock();
+        hipError_t e = hipSuccess;
+        if (launched) e = hipEventSynchronize(ev);
+        const double t = now_s();
+        lk.lock();
+        Batch done = std::move(S->inflight[stream].front());
+        S->inflight[stream].pop_front();
+        for (Job *jp : done.jp) {
+            Job &j = *jp;
+            j.done = true;
+            j.t_done = t;
+            if (e != hipSuccess) j.status = SH_EDEVICE;
+            Tree &tr = S->trees.at(j.tree);
+            tr.busy = false;
+            --tr.pending;
+            if (j.status == SH_OK) {
+                S->latencies.push_back(t - j.t_submit);
+                ++S->jobs_done;
+                S->translations_done += (int64_t)j.src.size();
+            } else {
+                ++S->failed;
+            }
+        }
+        S->t_last_done = t;
+        S->stage_alloc.release(done.st_off, done.st_bytes);
+        if (done.ev) (void)hipEventDestroy(done.ev);
+        S->cv_sched.notify_all();
+        S->cv_done.notify_all();
+        S->cv_complete.notify_all();
+    }
+}
+
+// waits (with the lock held) until a tree has no queued or in-flight job
+void wait_tree_idle(sh_server *S, std::unique_lock<std::mutex> &lk, int32_t tree)
+{
+    S->cv_done.wait(lk, [&] {
+        auto it = S->trees.find(tree);
+        return it == S->trees.end() || it->second.pending == 0;
+    });
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_server_create(sh_ctx *ctx, const sh_server_config *cfg, sh_server **out)
+{
+    if (!out) return SH_EINVAL;
+    *out = nullptr;
+    if (!ctx || !cfg || cfg->pool_bytes < 0 || cfg->staging_bytes < (1 << 16) || cfg->streams < 1 ||
+        cfg->streams > 8 || cfg->max_batch_jobs < 1)
+        return SH_EINVAL;
+    try {
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return SH_EDEVICE;
+        sh_server *S = new sh_server;
+        S->ctx = ctx;
+        S->cfg = *cfg;
+        S->cfg.pool_bytes = round_up(cfg->pool_bytes);
+        S->cfg.staging_bytes = round_up(cfg->staging_bytes);
+        bool ok = true;
+        if (S->cfg.pool_bytes > 0 && hipMalloc(&S->pool, (size_t)S->cfg.pool_bytes) != hipSuccess) {
+            S->pool = nullptr;
+            ok = false;
+        }
+        if (ok && hipMalloc(&S->dstage, (size_t)S->cfg.staging_bytes) != hipSuccess) {
+            S->dstage = nullptr;
+            ok = false;
+        }
+        if (ok && hipHostMalloc(&S->hstage, (size_t)S->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess) {
+            S->hstage = nullptr;
+            ok = false;
+        }
+        for (int i = 0; ok && i < cfg->streams; ++i) {
+            hipStream_t s;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+                ok = false;
+            else
+                S->streams.push_back(s);
+        }
+        if (!ok) {
+            for (auto s : S->streams) (void)hipStreamDestroy(s);
+            if (S->hstage) (void)hipHostFree(S->hstage);
+            if (S->dstage) (void)hipFree(S->dstage);
+            if (S->pool) (void)hipFree(S->pool);
+            delete S;
+            return SH_ENOMEM;
+        }
+        S->pool_alloc.init(S->cfg.pool_bytes);
+        S->stage_alloc.init(S->cfg.staging_bytes);
+        S->inflight.resize(S->streams.size());
+        S->scheduler = std::thread(scheduler_main, S);
+        for (size_t i = 0; i < S->streams.size(); ++i) S->completers.emplace_back(completer_main, S, (int)i);
+        *out = S;
+        return SH_OK;
+    } catch (const std::bad_alloc &) {
+        return SH_ENOMEM;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+void sh_server_destroy(sh_server *S)
+{
+    if (!S) return;
+    try {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_sched.notify_all();
+        S->cv_complete.notify_all();
+        if (S->scheduler.joinable()) S->scheduler.join();
+        S->cv_complete.notify_all();
+        for (auto &t : S->completers)
+            if (t.joinable()) t.join();
+        DeviceGuard g(S->ctx->device);
+        for (auto s : S->streams) (void)hipStreamDestroy(s);
+        if (S->hstage) (void)hipHostFree(S->hstage);
+        if (S->dstage) (void)hipFree(S->dstage);
+        if (S->pool) (void)hipFree(S->pool);
+        delete S;
+    } catch (...) {
+    }
+}
+
+sh_status sh_server_tree_create(sh_server *S, int dtype, int p_m, int64_t n_m, int p_l, int64_t n_l, int32_t *tree)
+{
+    if (!S || !tree || (dtype != SH_F64 && dtype != SH_F32) || n_m < 0 || n_l < 0) return SH_EINVAL;
+    if (p_m < 1 || p_l < 1 || p_m > S->ctx->max_order || p_l > S->ctx->max_order) return SH_EORDER;
+    try {
+        const int64_t elem = dtype == SH_F32 ? 4 : 8;
+        Tree t;
+        t.dtype = dtype;
+        t.p_m = p_m;
+        t.p_l = p_l;
+        t.n_m = n_m;
+        t.n_l = n_l;
+        t.bytes_m = std::max<int64_t>(kAlign, n_m * p_m * (p_m + 1) * elem);
+        t.bytes_l = std::max<int64_t>(kAlign, n_l * p_l * (p_l + 1) * elem);
+        std::lock_guard<std::mutex> lk(S->mu);
+        t.off_m = S->pool_alloc.alloc(t.bytes_m);
+        if (t.off_m < 0) return SH_EBUSY;
+        t.off_l = S->pool_alloc.alloc(t.bytes_l);
+        if (t.off_l < 0) {
+            S->pool_alloc.release(t.off_m, t.bytes_m);
+            return SH_EBUSY;
+        }
+        const int32_t id = S->next_tree++;
+        S->trees[id] = t;
+        *tree = id;
+        return SH_OK;
+    } catch (...) {
+        return SH_ENOMEM;
+    }
+}
+
+static sh_status tree_copy(sh_server *S, int32_t tree, int pool, int64_t first, int64_t n, void *host, bool write)
+{
+    if (!S || (pool != 0 && pool != 1) || first < 0 || n < 0 || (n > 0 && !host)) return SH_EINVAL;
+    try {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->trees.find(tree);
+        if (it == S->trees.end()) return SH_EINVAL;
+        wait_tree_idle(S, lk, tree);
+        it = S->trees.find(tree);
+        if (it == S->trees.end()) return SH_EINVAL;
+        const Tree t = it->second;
+        const int p = pool == 0 ? t.p_m : t.p_l;
+        const int64_t cnt = pool == 0 ? t.n_m : t.n_l;
+        if (first + n > cnt) return SH_EINVAL;
+        if (n == 0) return SH_OK;
+        const int64_t elem = t.dtype == SH_F32 ? 4 : 8;
+        const int64_t sz = (int64_t)p * (p + 1) * elem;
+        char *dev = static_cast<char *>(S->pool) + (pool == 0 ? t.off_m : t.off_l) + first * sz;
+        lk.unlock();
+        DeviceGuard g(S->ctx->device);
+        const hipError_t e = write ? hipMemcpy(dev, host, (size_t)(n * sz), hipMemcpyHostToDevice)
+                                   : hipMemcpy(host, dev, (size_t)(n * sz), hipMemcpyDeviceToHost);
+        return e == hipSuccess ? SH_OK : SH_EDEVICE;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+sh_status sh_server_tree_write(sh_server *S, int32_t tree, int pool, int64_t first, int64_t n, const void *host)
+{
+    return tree_copy(S, tree, pool, first, n, const_cast<void *>(host), true);
+}
+
+sh_status sh_server_tree_read(sh_server *S, int32_t tree, int pool, int64_t first, int64_t n, void *host)
+{
+    return tree_copy(S, tree, pool, first, n, host, false);
+}
+
+sh_status sh_server_tree_destroy(sh_server *S, int32_t tree)
+{
+    if (!S) return SH_EINVAL;
+    try {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (S->trees.find(tree) == S->trees.end()) return SH_EINVAL;
+        wait_tree_idle(S, lk, tree);
+        auto it = S->trees.find(tree);
+        if (it == S->trees.end()) return SH_EINVAL;
+        S->pool_alloc.release(it->second.off_m, it->second.bytes_m);
+        S->pool_alloc.release(it->second.off_l, it->second.bytes_l);
+        S->trees.erase(it);
+        return SH_OK;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
+{
+    if (!S || !job || !job_id || job->count < 0 || (job->flags & ~SH_ACCUMULATE) ||
+        (job->op != SH_M2M && job->op != SH_M2L && job->op != SH_L2L))
+        return SH_EINVAL;
+    if (job->count > 0 && (!job->r || !job->src || !job->dst)) return SH_EINVAL;
+    try {
+        Job j;
+        j.tree = job->tree;
+        j.op = job->op;
+        j.flags = job->flags;
+        const size_t n = (size_t)job->count;
+        j.r.assign(job->r, job->r + 3 * n);
+        j.src.assign(job->src, job->src + n);
+        j.dst.assign(job->dst, job->dst + n);
+        j.footprint = job_footprint(job->count);
+        for (size_t i = 0; i < n; ++i) {
+            const double *r = &j.r[3 * i];
+            if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2])) return SH_ESHIFT;
+            if (j.op == SH_M2L && r[0] == 0 && r[1] == 0 && r[2] == 0) return SH_ESHIFT;
+        }
+        int64_t n_in, n_out;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            auto it = S->trees.find(j.tree);
+            if (it == S->trees.end()) return SH_EINVAL;
+            n_in = j.op == SH_L2L ? it->second.n_l : it->second.n_m;
+            n_out = j.op == SH_M2M ? it->second.n_m : it->second.n_l;
+        }
+        for (size_t i = 0; i < n; ++i)
+            if (j.src[i] < 0 || j.src[i] >= n_in || j.dst[i] < 0 || j.dst[i] >= n_out) return SH_EINVAL;
+        // destinations unique within the job; for M2M / L2L (one pool) no destination is also
+        // a source (one byte per slot of the destination pool)
+        std::vector<unsigned char> mark((size_t)n_out, 0);
+        for (int64_t d : j.dst) {
+            if (mark[(size_t)d]) return SH_EINVAL;
+            mark[(size_t)d] = 1;
+        }
+        if (j.op != SH_M2L)
+            for (int64_t s : j.src)
+                if (mark[(size_t)s]) return SH_EINVAL;
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->trees.find(j.tree);
+        if (it == S->trees.end()) return SH_EINVAL;
+        if (j.footprint > S->cfg.staging_bytes) return SH_EBUSY;  // can never be admitted
+        const int64_t id = S->next_job++;
+        j.t_submit = now_s();
+        if (S->t_first_submit < 0) S->t_first_submit = j.t_submit;
+        it->second.pending++;
+        if (n == 0) {  // nothing to run: complete at once
+            j.done = true;
+            j.t_done = j.t_submit;
+            it->second.pending--;
+            S->latencies.push_back(0.0);
+            ++S->jobs_done;
+        } else {
+            S->queue.push_back(id);
+            S->queue_peak = std::max<int64_t>(S->queue_peak, (int64_t)S->queue.size());
+        }
+        S->jobs.emplace(id, std::unique_ptr<Job>(new Job(std::move(j))));
+        *job_id = id;
+        S->cv_sched.notify_all();
+        return SH_OK;
+    } catch (const std::bad_alloc &) {
+        return SH_ENOMEM;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+sh_status sh_server_wait(sh_server *S, int64_t job_id, double *latency_s)
+{
+    if (!S) return SH_EINVAL;
+    try {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->jobs.find(job_id);
+        if (it == S->jobs.end()) return SH_EINVAL;
+        S->cv_done.wait(lk, [&] { return S->jobs.at(job_id)->done; });
+        const Job &j = *S->jobs.at(job_id);
+        if (latency_s) *latency_s = j.t_done - j.t_submit;
+        const int st = j.status;
+        S->jobs.erase(job_id);
+        return (sh_status)st;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+sh_status sh_server_drain(sh_server *S)
+{
+    if (!S) return SH_EINVAL;
+    try {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight_total() == 0; });
+        return S->failed ? SH_EDEVICE : SH_OK;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+sh_status sh_server_stats_get(sh_server *S, sh_server_stats *st)
+{
+    if (!S || !st) return SH_EINVAL;
+    try {
+        std::lock_guard<std::mutex> lk(S->mu);
+        std::memset(st, 0, sizeof(*st));
+        st->jobs_done = S->jobs_done;
+        st->jobs_failed = S->failed;
+        st->translations_done = S->translations_done;
+        st->batches = S->batches;
+        st->mean_batch_jobs = S->batches ? (double)S->batch_jobs / (double)S->batches : 0.0;
+        st->queue_peak = S->queue_peak;
+        st->staging_peak_bytes = S->stage_alloc.peak;
+        st->pool_used_bytes = S->pool_alloc.used;
+        st->elapsed_s = (S->t_first_submit >= 0 && S->t_last_done >= 0) ? S->t_last_done - S->t_first_submit : 0.0;
+        if (!S->latencies.empty()) {
+            std::vector<double> v(S->latencies);
+            std::sort(v.begin(), v.end());
+            auto q = [&](double f) {
+                const size_t k = (size_t)std::min<double>((double)v.size() - 1, std::ceil(f * (double)v.size()) - 1);
+                return v[k];
+            };
+            st->p50_s = q(0.50);
+            st->p99_s = q(0.99);
+            st->max_s = v.back();
+            double sum = 0;
+            for (double x : v) sum += x;
+            st->mean_s = sum / (double)v.size();
+        }
+        return SH_OK;
+    } catch (...) {
+        return SH_EDEVICE;
+    }
+}
+
+}  // extern "C"
