@@ -112,7 +112,9 @@ def check_items(orc, dtype, op, p_in, p_out, r, C, got, what, base=None):
             ref = ref + b
             rl = rl + b if rl is not None else None
             r32 = r32 + b if r32 is not None else None
-        worst = max(worst, check(g, ref, po, OUT_KIND[name], TOL[dtype], f"{what} {name} {pi}->{po}", rl, r32))
+        cond = (orc, name, pi, rg, Cg) if dtype == sh.SH_F32 else None
+        worst = max(worst, check(g, ref, po, OUT_KIND[name], TOL[dtype], f"{what} {name} {pi}->{po}", rl, r32,
+                                 cond))
     return worst
 
 
