@@ -70,6 +70,8 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
                               ld_out % 2 == 0 && ld_in < (1 << 24) && ld_out < (1 << 24);
     if (pair_aligned && shfmm::lpt_available(op, f32, p_in, p_out))
         e = shfmm::launch_lpt(ctx->tabs, a, f32, s);
+    else if (pair_aligned && shfmm::big_available(p_in, p_out))
+        e = shfmm::launch_big(ctx->tabs, a, f32, s);
     else
         e = shfmm::launch_general(ctx->tabs, a, f32, s);
     return e == hipSuccess ? SH_OK : SH_EDEVICE;
@@ -190,6 +192,8 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk64[k].size() * 8); }
         for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk32[k].size() * 4); }
         for (int k = 0; k < 2; ++k) { offs.push_back(total); total += al(ht.pk64n[k].size() * 8); }
+        for (int k = 0; k < 4; ++k) { offs.push_back(total); total += al(ht.bsw[k / 2][k % 2].size() * 8); }
+        for (int k = 0; k < 6; ++k) { offs.push_back(total); total += al(ht.bz[k / 3][k % 3].size() * 8); }
         offs.push_back(total);
         total += 256;
         void *mem = nullptr;
@@ -237,6 +241,16 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         for (int k = 0; k < 2; ++k, ++idx) {
             ok &= hipMemcpy(base + offs[idx], ht.pk64n[k].data(), ht.pk64n[k].size() * 8, hipMemcpyHostToDevice) == hipSuccess;
             c->tabs.pk64n[k] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 4; ++k, ++idx) {
+            const auto &v = ht.bsw[k / 2][k % 2];
+            ok &= hipMemcpy(base + offs[idx], v.data(), v.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.bsw[k / 2][k % 2] = reinterpret_cast<const double *>(base + offs[idx]);
+        }
+        for (int k = 0; k < 6; ++k, ++idx) {
+            const auto &v = ht.bz[k / 3][k % 3];
+            ok &= hipMemcpy(base + offs[idx], v.data(), v.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+            c->tabs.bz[k / 3][k % 3] = reinterpret_cast<const double *>(base + offs[idx]);
         }
         c->err_flag = reinterpret_cast<int *>(base + offs[idx]);
         ok &= hipMemset(c->err_flag, 0, sizeof(int)) == hipSuccess;

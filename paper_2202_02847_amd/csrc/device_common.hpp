@@ -24,6 +24,8 @@ struct DevTables {
     const double *pk64[2];   // packed swap tables, [0] M side (F, G), [1] L side (FL, GL)
     const float *pk32[2];
     const double *pk64n[2];
+    const double *bsw[2][2];  // block-kernel swap fragments [basis: 0 paper, 1 normalised][side: 0 M, 1 L]
+    const double *bz[2][3];   // block-kernel z fragments [basis][op]
     int P;
 };
 

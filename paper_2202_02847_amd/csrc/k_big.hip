@@ -1,0 +1,386 @@
+// Block kernel for large orders (up to 31): the rotation scheme of Section 3.4 on the FP64
+// matrix cores, 16 translations at a time.
+//
+// A lane-per-translation kernel needs 64 solids in LDS, which no longer fits above order 16.
+// Here a workgroup holds 16 solids in LDS, coefficient-major (X[c][t], t = translation), and
+// every O(P^3) step becomes a small GEMM whose N dimension is the 16 translations:
+//   * swaps: the chequerboard of F / G splits each row's swap into two dense blocks by the
+//     parity of the output order m (m + l + n even for the real part, odd for the imaginary
+//     part), each at most 16 x 16 up to degree 31: one 16 x 16 x 4 FP64 MFMA per K step, with
+//     A = table fragments (prepared on the host in operand order, read from L2) and
+//     B = the row's coefficients of the 16 translations (LDS);
+//   * z-translation: per column m, the column's Hankel / Toeplitz matrix times the column of
+//     the 16 rotated solids, real and imaginary parts as two GEMMs sharing the fragments.
+// The O(P^2) steps (scaling, z-rotations) run on the VALU between the GEMMs, on the MFMA
+// output registers.  Rows (forward and backward rotations) and columns (z-step) are spread
+// over the 4 wavefronts in snake order; LDS barriers separate the phases.
+// FP64 16x16x4 MFMA operand layout (checked on the device): A[l % 16][l / 16],
+// B[l / 16][l % 16], D[4 j + l / 16][l % 16] for lane l and output register j.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace shfmm {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kBT = 16;  // translations per block
+
+template <typename Real>
+struct Pair2;
+template <>
+struct Pair2<double> {
+    using T = double2;
+};
+template <>
+struct Pair2<float> {
+    using T = float2;
+};
+
+// LDS carve-up (in doubles): X[S][16] | powers[4][32][16] | scale_in[32][16] | scale_out[32][16]
+// | in offsets[16] | out offsets[16] | shifts[16][3] | bad flags[16]
+struct BigLds {
+    double *X, *pw, *scin, *scout, *r;
+    int64_t *ioff, *ooff;
+    int *bad;
+};
+
+__host__ __device__ constexpr size_t big_lds_doubles(int PM)
+{
+    return (size_t)PM * (PM + 1) * kBT + 4 * kBigOrder * kBT + 2 * kBigOrder * kBT + 2 * kBT + 3 * kBT + kBT / 2;
+}
+
+__device__ __forceinline__ BigLds big_lds(double *sm, int PM)
+{
+    BigLds L;
+    L.X = sm;
+    L.pw = sm + (size_t)PM * (PM + 1) * kBT;
+    L.scin = L.pw + 4 * kBigOrder * kBT;
+    L.scout = L.scin + kBigOrder * kBT;
+    L.ioff = reinterpret_cast<int64_t *>(L.scout + kBigOrder * kBT);
+    L.ooff = L.ioff + kBT;
+    L.r = reinterpret_cast<double *>(L.ooff + kBT);
+    L.bad = reinterpret_cast<int *>(L.r + 3 * kBT);
+    return L;
+}
+
+__device__ __forceinline__ int pos(int n, int m) { return n * (n + 1) + 2 * m; }
+
+// degree n of pair index p (p = n(n+1)/2 + m)
+__device__ __forceinline__ int pair_degree(int p)
+{
+    int n = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    while ((n + 1) * (n + 2) / 2 <= p) ++n;
+    while (n * (n + 1) / 2 > p) --n;
+    return n;
+}
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.
+__device__ __forceinline__ void swap_row(const double *__restrict__ frag, const double *X, int n, int lane,
+                                         d4 (&D)[2][2])
+{
+    const int ks_n = big_ks(n);
+    const double *F = frag + big_swap_off(n);
+    const int t = lane & 15, kg = lane >> 4;
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int pl = (n + pm + q) & 1;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < ks_n; ++ks) {
+                const double a = F[((pm * 2 + q) * ks_n + ks) * 64 + lane];
+                const int lc = 2 * (4 * ks + kg) + pl;
+                const double b = lc <= n ? X[(n * (n + 1) + 2 * lc + q) * kBT + t] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
+            D[pm][q] = acc;
+        }
+}
+
+// Writes the D blocks of row n back to X, after an optional rotation by e^{+-i m angle}
+// (powers k, k + 1 of the table) and an optional scale per translation.
+__device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int lane, const d4 (&D)[2][2], int rot_k,
+                                          double sgn, const double *scale)
+{
+    const int t = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = 2 * (4 * j + g) + pm;
+            if (m > n) continue;
+            double re = D[pm][0][j], im = D[pm][1][j];
+            if (rot_k >= 0) {
+                const double c = L.pw[(rot_k * kBigOrder + m) * kBT + t];
+                const double s = sgn * L.pw[((rot_k + 1) * kBigOrder + m) * kBT + t];
+                const double a = re;
+                re = a * c - im * s;
+                im = a * s + im * c;
+            }
+            if (scale) {
+                const double f = scale[n * kBT + t];
+                re *= f;
+                im *= f;
+            }
+            X[pos(n, m) * kBT + t] = re;
+            X[(pos(n, m) + 1) * kBT + t] = m ? im : 0.0;
+        }
+}
+
+// One block of up to 16 translations whose offsets and shifts are in L (t >= nt repeat the
+// last valid translation and are not stored).
+template <typename Real, int OP>
+__device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p_out, int nt, const Real *__restrict__ ain,
+                          Real *__restrict__ aout, bool acc_out, int *err)
+{
+    using R2 = typename Pair2<Real>::T;
+    constexpr int basis = sizeof(Real) == 4 ? 1 : 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int PM = p_in > p_out ? p_in : p_out;
+    double *X = L.X;
+
+    // ---- geometry, powers and scales, one thread per translation ----
+    if (tid < kBT) {
+        const int t = tid;
+        const Geometry g = shift_geometry(L.r[3 * t], L.r[3 * t + 1], L.r[3 * t + 2]);
+        const bool ok = g.valid == 1;
+        L.bad[t] = ok ? 0 : (g.valid == 0 ? 1 : 2);
+        const double ca = ok ? g.ca : 1.0, sa = ok ? g.sa : 0.0, cb = ok ? g.cb : 1.0, sb = ok ? g.sb : 0.0;
+        const double R = ok ? g.R : 1.0, s = ok ? g.s : 1.0;
+        double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0, rn = 1.0, sn = 1.0;
+        for (int m = 0; m < PM; ++m) {
+            L.pw[(0 * kBigOrder + m) * kBT + t] = c1;
+            L.pw[(1 * kBigOrder + m) * kBT + t] = s1;
+            L.pw[(2 * kBigOrder + m) * kBT + t] = c2;
+            L.pw[(3 * kBigOrder + m) * kBT + t] = s2;
+            const double t1 = c1 * ca - s1 * sa;
+            s1 = c1 * sa + s1 * ca;
+            c1 = t1;
+            const double t2 = c2 * cb - s2 * sb;
+            s2 = c2 * sb + s2 * cb;
+            c2 = t2;
+            // rn = R^m, sn = s^m
+            L.scin[m * kBT + t] = (OP == OP_L2L) ? rn : sn * s;
+            L.scout[m * kBT + t] = (OP == OP_M2M) ? rn * R : sn;
+            rn *= R;
+            sn *= s;
+        }
+    }
+    __syncthreads();
+
+    // ---- load: scale and rotate by alpha; rows >= p_in are zero ----
+    {
+        const int npair = PM * (PM + 1) / 2;
+        for (int idx = tid; idx < npair * kBT; idx += 256) {
+            const int t = idx & 15, p = idx >> 4;
+            const int n = pair_degree(p), m = p - n * (n + 1) / 2;
+            double re = 0.0, im = 0.0;
+            if (n < p_in) {
+                const R2 v = *reinterpret_cast<const R2 *>(ain + L.ioff[t] + 2 * p);
+                const double f = L.scin[n * kBT + t];
+                const double a = (double)v.x * f, b = m ? (double)v.y * f : 0.0;
+                const double c = L.pw[(0 * kBigOrder + m) * kBT + t], s = L.pw[(1 * kBigOrder + m) * kBT + t];
+                re = a * c - b * s;
+                im = m ? a * s + b * c : 0.0;
+            }
+            X[(2 * p) * kBT + t] = re;
+            X[(2 * p + 1) * kBT + t] = im;
+        }
+    }
+    __syncthreads();
+
+    const int fw = (OP == OP_L2L) ? 1 : 0, bw = (OP == OP_M2M) ? 0 : 1;
+    const double *Ffw = tab.bsw[basis][fw], *Fbw = tab.bsw[basis][bw];
+
+    // ---- forward rotation, rows in snake order over the wavefronts ----
+    for (int n0 = 0; n0 < p_in; n0 += 4) {
+        const int n = n0 + (((n0 >> 2) & 1) ? 3 - wave : wave);
+        if (n >= p_in) continue;
+        d4 D[2][2];
+        swap_row(Ffw, X, n, lane, D);
+        write_row(X, L, n, lane, D, 2, 1.0, nullptr);  // rotate by beta
+        swap_row(Ffw, X, n, lane, D);
+        write_row(X, L, n, lane, D, -1, 1.0, nullptr);
+    }
+    __syncthreads();
+
+    // ---- z-translation, columns in snake order ----
+    {
+        const double *Zt = tab.bz[basis][OP];
+        const int t = lane & 15, kg = lane >> 4;
+        for (int m0 = 0; m0 < p_out; m0 += 4) {
+            const int m = m0 + (((m0 >> 2) & 1) ? 3 - wave : wave);
+            if (m >= p_out) continue;
+            const double *Z = Zt + big_z_off(m);
+            const int kz = big_kz(m);
+            const int mto = (p_out - m + 15) / 16;
+            const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
+            double b[2][8];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int i = m + 4 * ks + kg;
+                    b[q][ks] = (ks < ki && i < p_in) ? X[(pos(i, m) + q) * kBT + t] : 0.0;
+                }
+            d4 res[2][2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                d4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+                if (mt < mto) {
+#pragma unroll
+                    for (int ks = 0; ks < 8; ++ks) {
+                        if (ks >= ki) break;
+                        const double a = Z[(mt * kz + ks) * 64 + lane];
+                        a0 = mfma64(a, b[0][ks], a0);
+                        a1 = mfma64(a, b[1][ks], a1);
+                    }
+                }
+                res[0][mt] = a0;
+                res[1][mt] = a1;
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                if (mt >= mto) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = m + 16 * mt + 4 * j + kg;
+                    if (o >= p_out) continue;
+                    X[pos(o, m) * kBT + t] = res[0][mt][j];
+                    X[(pos(o, m) + 1) * kBT + t] = m ? res[1][mt][j] : 0.0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- backward rotation, unscale ----
+    for (int n0 = 0; n0 < p_out; n0 += 4) {
+        const int n = n0 + (((n0 >> 2) & 1) ? 3 - wave : wave);
+        if (n >= p_out) continue;
+        d4 D[2][2];
+        swap_row(Fbw, X, n, lane, D);
+        write_row(X, L, n, lane, D, 2, -1.0, nullptr);   // rotate by -beta
+        swap_row(Fbw, X, n, lane, D);
+        write_row(X, L, n, lane, D, 0, -1.0, L.scout);   // rotate by -alpha, unscale
+    }
+    __syncthreads();
+
+    // ---- store ----
+    {
+        const int npair = p_out * (p_out + 1) / 2;
+        for (int idx = tid; idx < npair * kBT; idx += 256) {
+            const int t = idx & 15, p = idx >> 4;
+            if (t >= nt) continue;
+            const int n = pair_degree(p), m = p - n * (n + 1) / 2;
+            R2 *dp = reinterpret_cast<R2 *>(aout + L.ooff[t] + 2 * p);
+            double re = X[(2 * p) * kBT + t], im = m ? X[(2 * p + 1) * kBT + t] : 0.0;
+            const int bad = L.bad[t];
+            const bool ident = bad == 1 && OP != OP_M2L;
+            if (bad) {
+                if (ident) {  // zero shift of M2M / L2L: identity, truncated / zero-padded
+                    const bool keep = n < p_in;
+                    re = keep ? (double)ain[L.ioff[t] + 2 * p] : 0.0;
+                    im = (keep && m) ? (double)ain[L.ioff[t] + 2 * p + 1] : 0.0;
+                } else {
+                    re = im = __builtin_nan("");
+                    if (p == 0) raise_device_error(err, -3);
+                }
+            }
+            if (acc_out && (!bad || ident)) {
+                const R2 old = *dp;
+                re += (double)old.x;
+                if (m) im += (double)old.y;
+            }
+            R2 w;
+            w.x = (Real)re;
+            w.y = (Real)im;
+            *dp = w;
+        }
+    }
+    __syncthreads();
+}
+
+// Batched form: translation i = 16 b + t of the call.
+template <typename Real, int OP, bool IDX>
+__global__ __launch_bounds__(256) void k_big(DevTables tab, TransArgs a)
+{
+    extern __shared__ double sm[];
+    const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
+    const BigLds L = big_lds(sm, PM);
+    const Real *ain = reinterpret_cast<const Real *>(a.in);
+    Real *aout = reinterpret_cast<Real *>(a.out);
+    const Real *rr = reinterpret_cast<const Real *>(a.r);
+    const int64_t nblk = (a.count + kBT - 1) / kBT;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t first = blk * kBT;
+        const int nt = (int)((a.count - first) < kBT ? (a.count - first) : kBT);
+        if (threadIdx.x < kBT) {
+            const int t = threadIdx.x;
+            const int64_t i = first + (t < nt ? t : nt - 1);
+            const int64_t si = IDX ? a.src[i] : i, di = IDX ? a.dst[i] : i;
+            L.ioff[t] = si * a.ld_in;
+            L.ooff[t] = di * a.ld_out;
+            L.r[3 * t] = (double)rr[3 * i];
+            L.r[3 * t + 1] = (double)rr[3 * i + 1];
+            L.r[3 * t + 2] = (double)rr[3 * i + 2];
+        }
+        __syncthreads();
+        big_block<Real, OP>(tab, L, a.p_in, a.p_out, nt, ain, aout, (a.flags & 1u) != 0, a.err);
+    }
+}
+
+template <typename Real, int OP, bool IDX>
+hipError_t launch_big_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
+{
+    const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
+    const size_t smem = big_lds_doubles(PM) * sizeof(double);
+    const void *fn = reinterpret_cast<const void *>(&k_big<Real, OP, IDX>);
+    int dev = 0, cu = 256, occ = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, smem) != hipSuccess || occ < 1) occ = 1;
+    const int64_t nblk = (a.count + kBT - 1) / kBT;
+    const int64_t res = (int64_t)cu * occ;
+    const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(256);
+    hipLaunchKernelGGL((k_big<Real, OP, IDX>), grid, block, smem, s, tab, a);
+    return hipGetLastError();
+}
+
+template <typename Real, bool IDX>
+hipError_t launch_big_op(const DevTables &tab, const TransArgs &a, hipStream_t s)
+{
+    if (a.op == OP_M2M) return launch_big_one<Real, OP_M2M, IDX>(tab, a, s);
+    if (a.op == OP_M2L) return launch_big_one<Real, OP_M2L, IDX>(tab, a, s);
+    return launch_big_one<Real, OP_L2L, IDX>(tab, a, s);
+}
+
+}  // namespace
+
+bool big_available(int p_in, int p_out)
+{
+    const int PM = p_in > p_out ? p_in : p_out;
+    return PM >= 2 && PM < kBigOrder && big_lds_doubles(PM) * sizeof(double) <= 160 * 1024;
+}
+
+size_t big_lds_bytes(int PM) { return big_lds_doubles(PM) * sizeof(double); }
+
+hipError_t launch_big(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s)
+{
+    if (a.count <= 0) return hipSuccess;
+    const bool idx = a.src != nullptr;
+    if (f32) return idx ? launch_big_op<float, true>(tab, a, s) : launch_big_op<float, false>(tab, a, s);
+    return idx ? launch_big_op<double, true>(tab, a, s) : launch_big_op<double, false>(tab, a, s);
+}
+
+}  // namespace shfmm

@@ -93,6 +93,12 @@ namespace lpt {
 int resident_workgroups(const void *fn);
 }
 
+// Block kernel on the FP64 matrix cores (k_big.hip): 16 translations per workgroup pass, any
+// p_in, p_out up to 31 (FP32 I/O in the normalised basis, FP64 arithmetic).
+bool big_available(int p_in, int p_out);
+size_t big_lds_bytes(int PM);
+hipError_t launch_big(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s);
+
 // Highest order with a fixed-order (lane-per-translation) kernel.
 constexpr int kLptMaxOrder = 16;
 

@@ -1,5 +1,6 @@
 // Exact construction of the swap matrices and z-axis coefficients.  See tables.hpp.
 #include "tables.hpp"
+#include "layout.hpp"
 
 #include <cmath>
 #include <mutex>
@@ -212,6 +213,29 @@ void build_tables(int P, HostTables &t)
         pack(t.swap32[2 * side], t.swap32[2 * side + 1], t.pk32[side]);
         pack(t.swap64n[2 * side], t.swap64n[2 * side + 1], t.pk64n[side]);
     }
+    // MFMA fragments of the block kernel, from the dense tables rounded above
+    for (int basis = 0; basis < 2; ++basis) {
+        for (int side = 0; side < 2; ++side) {
+            auto &out = t.bsw[basis][side];
+            out.assign(big_swap_off(kBigOrder), 0.0);
+            for (int n = 0; n < kBigOrder && n < P; ++n) {
+                const int64_t off = swap_offset(n);
+                for (int pm = 0; pm < 2; ++pm)
+                    for (int q = 0; q < 2; ++q) {
+                        const auto &dense = basis ? t.swap64n[2 * side + q] : t.swap64[2 * side + q];
+                        const int pl = (n + pm + q) & 1;
+                        for (int ks = 0; ks < big_ks(n); ++ks)
+                            for (int l = 0; l < 64; ++l) {
+                                const int m = 2 * (l % 16) + pm, lc = 2 * (4 * ks + l / 16) + pl;
+                                double v = 0.0;
+                                if (m <= n && lc <= n && !(q == 1 && (m == 0 || lc == 0)))
+                                    v = dense[off + m * (n + 1) + lc];
+                                out[big_swap_off(n) + ((pm * 2 + q) * big_ks(n) + ks) * 64 + l] = v;
+                            }
+                    }
+            }
+        }
+    }
     for (int k = 0; k < 3; ++k) {
         t.z64[k].assign(z_table_size(P), 0.0);
         t.z32[k].assign(z_table_size(P), 0.0f);
@@ -226,6 +250,20 @@ void build_tables(int P, HostTables &t)
                     t.z32[k][at] = (float)cn;
                     t.z64n[k][at] = (double)cn;
                 }
+        }
+        for (int basis = 0; basis < 2; ++basis) {
+            auto &out = t.bz[basis][k];
+            out.assign(big_z_off(kBigOrder), 0.0);
+            for (int m = 0; m < kBigOrder && m < P; ++m)
+                for (int mt = 0; mt < big_mt(m); ++mt)
+                    for (int ks = 0; ks < big_kz(m); ++ks)
+                        for (int l = 0; l < 64; ++l) {
+                            const int o = m + 16 * mt + l % 16, i = m + 4 * ks + l / 16;
+                            double v = 0.0;
+                            if (o < kBigOrder && i < kBigOrder && o < P && i < P)
+                                v = (double)z_coefficient((ZKind)k, m, o, i, basis == 1);
+                            out[big_z_off(m) + (mt * big_kz(m) + ks) * 64 + l] = v;
+                        }
         }
     }
 }

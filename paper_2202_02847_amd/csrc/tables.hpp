@@ -68,6 +68,10 @@ struct HostTables {
     std::vector<double> pk64[2];
     std::vector<float> pk32[2];
     std::vector<double> pk64n[2];
+    // MFMA fragments of the block kernel (layout.hpp): [basis: 0 paper, 1 normalised][side] and
+    // [basis][op]
+    std::vector<double> bsw[2][2];
+    std::vector<double> bz[2][3];
 };
 
 // Builds every table for orders up to P (1 <= P <= kMaxOrder); sh_create uses kMaxOrder.
