@@ -84,27 +84,52 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.
-__device__ __forceinline__ void swap_row(const double *__restrict__ frag, const double *X, int n, int lane,
-                                         d4 (&D)[2][2])
+// Operator fragments of row n (both parities and parts, every K step; K steps past the
+// row's count are never used).  Both swaps of a row use the same table.
+struct RowFrag {
+    double a[2][2][4];
+};
+__device__ __forceinline__ void load_row_frag(const double *__restrict__ frag, int n, int lane, RowFrag &f)
 {
     const int ks_n = big_ks(n);
     const double *F = frag + big_swap_off(n);
-    const int t = lane & 15, kg = lane >> 4;
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int pl = (n + pm + q) & 1;
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < ks_n; ++ks) {
-                const double a = F[((pm * 2 + q) * ks_n + ks) * 64 + lane];
-                const int lc = 2 * (4 * ks + kg) + pl;
-                const double b = lc <= n ? X[(n * (n + 1) + 2 * lc + q) * kBT + t] : 0.0;
-                acc = mfma64(a, b, acc);
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                f.a[pm][q][ks] = ks < ks_n ? F[((pm * 2 + q) * ks_n + ks) * 64 + lane] : 0.0;
+}
+
+// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.  All of the
+// row's B values are read from LDS before the first product.
+__device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, int n, int lane, d4 (&D)[2][2])
+{
+    const int ks_n = big_ks(n);
+    const int t = lane & 15, kg = lane >> 4;
+    double b[2][2][4];
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int lc = 2 * (4 * ks + kg) + ((n + pm + q) & 1);
+                b[pm][q][ks] = (ks < ks_n && lc <= n) ? X[(n * (n + 1) + 2 * lc + q) * kBT + t] : 0.0;
             }
-            D[pm][q] = acc;
-        }
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) D[pm][q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        if (ks >= ks_n) break;
+#pragma unroll
+        for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) D[pm][q] = mfma64(f.a[pm][q][ks], b[pm][q][ks], D[pm][q]);
+    }
 }
 
 // Writes the D blocks of row n back to X, after an optional rotation by e^{+-i m angle}
@@ -179,23 +204,37 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     }
     __syncthreads();
 
-    // ---- load: scale and rotate by alpha; rows >= p_in are zero ----
+    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Each thread issues 8
+    // loads before it uses any, so they are in flight together ----
     {
-        const int npair = PM * (PM + 1) / 2;
-        for (int idx = tid; idx < npair * kBT; idx += 256) {
-            const int t = idx & 15, p = idx >> 4;
-            const int n = pair_degree(p), m = p - n * (n + 1) / 2;
-            double re = 0.0, im = 0.0;
-            if (n < p_in) {
-                const R2 v = *reinterpret_cast<const R2 *>(ain + L.ioff[t] + 2 * p);
-                const double f = L.scin[n * kBT + t];
-                const double a = (double)v.x * f, b = m ? (double)v.y * f : 0.0;
-                const double c = L.pw[(0 * kBigOrder + m) * kBT + t], s = L.pw[(1 * kBigOrder + m) * kBT + t];
-                re = a * c - b * s;
-                im = m ? a * s + b * c : 0.0;
+        constexpr int U = 8;
+        const int total = PM * (PM + 1) / 2 * kBT;
+        for (int base = 0; base < total; base += 256 * U) {
+            R2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + 256 * u;
+                const int t = idx & 15, p = idx >> 4;
+                const int n = idx < total ? pair_degree(p) : PM;
+                v[u] = (n < p_in) ? *reinterpret_cast<const R2 *>(ain + L.ioff[t] + 2 * p) : R2{};
             }
-            X[(2 * p) * kBT + t] = re;
-            X[(2 * p + 1) * kBT + t] = im;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + 256 * u;
+                if (idx >= total) continue;
+                const int t = idx & 15, p = idx >> 4;
+                const int n = pair_degree(p), m = p - n * (n + 1) / 2;
+                double re = 0.0, im = 0.0;
+                if (n < p_in) {
+                    const double f = L.scin[n * kBT + t];
+                    const double a = (double)v[u].x * f, b = m ? (double)v[u].y * f : 0.0;
+                    const double c = L.pw[(0 * kBigOrder + m) * kBT + t], s = L.pw[(1 * kBigOrder + m) * kBT + t];
+                    re = a * c - b * s;
+                    im = m ? a * s + b * c : 0.0;
+                }
+                X[(2 * p) * kBT + t] = re;
+                X[(2 * p + 1) * kBT + t] = im;
+            }
         }
     }
     __syncthreads();
@@ -203,15 +242,24 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     const int fw = (OP == OP_L2L) ? 1 : 0, bw = (OP == OP_M2M) ? 0 : 1;
     const double *Ffw = tab.bsw[basis][fw], *Fbw = tab.bsw[basis][bw];
 
-    // ---- forward rotation, rows in snake order over the wavefronts ----
-    for (int n0 = 0; n0 < p_in; n0 += 4) {
-        const int n = n0 + (((n0 >> 2) & 1) ? 3 - wave : wave);
-        if (n >= p_in) continue;
-        d4 D[2][2];
-        swap_row(Ffw, X, n, lane, D);
-        write_row(X, L, n, lane, D, 2, 1.0, nullptr);  // rotate by beta
-        swap_row(Ffw, X, n, lane, D);
-        write_row(X, L, n, lane, D, -1, 1.0, nullptr);
+    // ---- forward rotation, rows in snake order over the wavefronts; the next row's
+    // fragments are fetched while the current row is transformed ----
+    {
+        auto row_of = [&](int n0) { return n0 + (((n0 >> 2) & 1) ? 3 - wave : wave); };
+        RowFrag cur, nxt;
+        if (row_of(0) < p_in) load_row_frag(Ffw, row_of(0), lane, cur);
+        for (int n0 = 0; n0 < p_in; n0 += 4) {
+            const int n = row_of(n0);
+            if (n >= p_in) break;
+            const int nn = row_of(n0 + 4);
+            if (nn < p_in) load_row_frag(Ffw, nn, lane, nxt);
+            d4 D[2][2];
+            swap_row(cur, X, n, lane, D);
+            write_row(X, L, n, lane, D, 2, 1.0, nullptr);  // rotate by beta
+            swap_row(cur, X, n, lane, D);
+            write_row(X, L, n, lane, D, -1, 1.0, nullptr);
+            cur = nxt;
+        }
     }
     __syncthreads();
 
@@ -234,6 +282,12 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
                     const int i = m + 4 * ks + kg;
                     b[q][ks] = (ks < ki && i < p_in) ? X[(pos(i, m) + q) * kBT + t] : 0.0;
                 }
+            double za[2][8];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    za[mt][ks] = (mt < mto && ks < ki) ? Z[(mt * kz + ks) * 64 + lane] : 0.0;
             d4 res[2][2];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
@@ -242,9 +296,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 #pragma unroll
                     for (int ks = 0; ks < 8; ++ks) {
                         if (ks >= ki) break;
-                        const double a = Z[(mt * kz + ks) * 64 + lane];
-                        a0 = mfma64(a, b[0][ks], a0);
-                        a1 = mfma64(a, b[1][ks], a1);
+                        a0 = mfma64(za[mt][ks], b[0][ks], a0);
+                        a1 = mfma64(za[mt][ks], b[1][ks], a1);
                     }
                 }
                 res[0][mt] = a0;
@@ -266,14 +319,22 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     __syncthreads();
 
     // ---- backward rotation, unscale ----
-    for (int n0 = 0; n0 < p_out; n0 += 4) {
-        const int n = n0 + (((n0 >> 2) & 1) ? 3 - wave : wave);
-        if (n >= p_out) continue;
-        d4 D[2][2];
-        swap_row(Fbw, X, n, lane, D);
-        write_row(X, L, n, lane, D, 2, -1.0, nullptr);   // rotate by -beta
-        swap_row(Fbw, X, n, lane, D);
-        write_row(X, L, n, lane, D, 0, -1.0, L.scout);   // rotate by -alpha, unscale
+    {
+        auto row_of = [&](int n0) { return n0 + (((n0 >> 2) & 1) ? 3 - wave : wave); };
+        RowFrag cur, nxt;
+        if (row_of(0) < p_out) load_row_frag(Fbw, row_of(0), lane, cur);
+        for (int n0 = 0; n0 < p_out; n0 += 4) {
+            const int n = row_of(n0);
+            if (n >= p_out) break;
+            const int nn = row_of(n0 + 4);
+            if (nn < p_out) load_row_frag(Fbw, nn, lane, nxt);
+            d4 D[2][2];
+            swap_row(cur, X, n, lane, D);
+            write_row(X, L, n, lane, D, 2, -1.0, nullptr);   // rotate by -beta
+            swap_row(cur, X, n, lane, D);
+            write_row(X, L, n, lane, D, 0, -1.0, L.scout);   // rotate by -alpha, unscale
+            cur = nxt;
+        }
     }
     __syncthreads();
 
@@ -365,7 +426,62 @@ hipError_t launch_big_op(const DevTables &tab, const TransArgs &a, hipStream_t s
     return launch_big_one<Real, OP_L2L, IDX>(tab, a, s);
 }
 
+// Work-list form: one task (up to 16 items of one operation sharing (p_in, p_out)) per
+// workgroup pass; the LDS is sized for the bin's largest order.
+template <typename Real, int OP>
+__global__ __launch_bounds__(256) void k_big_list(DevTables tab, ListArgs la)
+{
+    extern __shared__ double sm[];
+    const Real *ain = reinterpret_cast<const Real *>(la.arena_in);
+    Real *aout = reinterpret_cast<Real *>(la.arena_out);
+    for (int64_t task = blockIdx.x; task < la.ntasks; task += gridDim.x) {
+        const ListTask tk = la.tasks[task];
+        const int p_in = tk.p_in, p_out = tk.p_out, nt = tk.count;
+        const BigLds L = big_lds(sm, p_in > p_out ? p_in : p_out);
+        if (threadIdx.x < kBT) {
+            const int t = threadIdx.x;
+            const ListItem &it = la.items[tk.first + (t < nt ? t : nt - 1)];
+            L.ioff[t] = it.in_off;
+            L.ooff[t] = it.out_off;
+            L.r[3 * t] = it.r[0];
+            L.r[3 * t + 1] = it.r[1];
+            L.r[3 * t + 2] = it.r[2];
+        }
+        __syncthreads();
+        big_block<Real, OP>(tab, L, p_in, p_out, nt, ain, aout, (la.flags & 1u) != 0, la.err);
+    }
+}
+
+template <typename Real, int OP>
+hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pmax, hipStream_t s)
+{
+    const size_t smem = big_lds_doubles(pmax) * sizeof(double);
+    const void *fn = reinterpret_cast<const void *>(&k_big_list<Real, OP>);
+    int dev = 0, cu = 256, occ = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, smem) != hipSuccess || occ < 1) occ = 1;
+    const int64_t res = (int64_t)cu * occ;
+    const dim3 grid((unsigned)(la.ntasks < res ? la.ntasks : res)), block(256);
+    hipLaunchKernelGGL((k_big_list<Real, OP>), grid, block, smem, s, tab, la);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_big_list_op(const DevTables &tab, const ListArgs &la, int op, int pmax, hipStream_t s)
+{
+    if (op == OP_M2M) return launch_big_list_one<Real, OP_M2M>(tab, la, pmax, s);
+    if (op == OP_M2L) return launch_big_list_one<Real, OP_M2L>(tab, la, pmax, s);
+    return launch_big_list_one<Real, OP_L2L>(tab, la, pmax, s);
+}
+
 }  // namespace
+
+hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, hipStream_t s)
+{
+    if (la.ntasks <= 0) return hipSuccess;
+    if (pmax < 1 || pmax >= kBigOrder) return hipErrorInvalidValue;
+    return f32 ? launch_big_list_op<float>(tab, la, op, pmax, s) : launch_big_list_op<double>(tab, la, op, pmax, s);
+}
 
 bool big_available(int p_in, int p_out)
 {

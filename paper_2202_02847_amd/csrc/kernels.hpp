@@ -98,6 +98,9 @@ int resident_workgroups(const void *fn);
 bool big_available(int p_in, int p_out);
 size_t big_lds_bytes(int PM);
 hipError_t launch_big(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s);
+// Work-list form: tasks of up to 16 items of operation op sharing (p_in, p_out); pmax = the
+// largest order of the launch's tasks (sizes the LDS), below 32.
+hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, hipStream_t s);
 
 // Highest order with a fixed-order (lane-per-translation) kernel.
 constexpr int kLptMaxOrder = 16;

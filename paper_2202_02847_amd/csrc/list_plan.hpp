@@ -12,9 +12,9 @@
 
 namespace shfmm {
 
-// Kernel mapping of a bin: lane-per-translation with 64- or 32-item tasks, or one wavefront
-// per translation.
-enum ListMapping { MAP_LPT64 = 0, MAP_LPT32 = 1, MAP_GENERAL = 2 };
+// Kernel mapping of a bin: lane-per-translation with 64- or 32-item tasks, one wavefront per
+// translation, or the matrix-core block kernel with 16-item tasks (orders 17..31).
+enum ListMapping { MAP_LPT64 = 0, MAP_LPT32 = 1, MAP_GENERAL = 2, MAP_BLOCK = 3 };
 
 struct ListBin {
     int mapping = MAP_LPT64;
@@ -32,7 +32,8 @@ struct ListBin {
 using MappingChoice = std::function<int(ListBin &bin, const std::vector<ListItem> &group)>;
 
 // Groups validated items by operation and order (lane-per-translation bins per (op, bucket),
-// wavefront bins per (order class, width)), reorders `items` bin by bin (largest orders
+// block-kernel bins per (op, order class) for orders 17..31, wavefront bins per (order class,
+// width) above), reorders `items` bin by bin (largest orders
 // first inside a bin), cuts the lane-per-translation bins into tasks (appended to `tasks`)
 // and orders the bins largest first.  Returns SH_OK or SH_EDEVICE (from `choose`).
 sh_status bin_items(int dtype, std::vector<ListItem> &items, std::vector<ListTask> &tasks,

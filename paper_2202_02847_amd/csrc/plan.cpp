@@ -33,6 +33,7 @@ using shfmm::ListArgs;
 using shfmm::ListItem;
 using shfmm::ListTask;
 using shfmm::ListBin;
+using shfmm::MAP_BLOCK;
 using shfmm::MAP_GENERAL;
 using shfmm::MAP_LPT32;
 using shfmm::MAP_LPT64;
@@ -44,7 +45,10 @@ static_assert(offsetof(sh_item, r) == offsetof(ListItem, r), "sh_item layout");
 
 namespace {
 
-const char *mapping_name(int m) { return m == MAP_LPT64 ? "lpt64" : m == MAP_LPT32 ? "lpt32" : "wave"; }
+const char *mapping_name(int m)
+{
+    return m == MAP_LPT64 ? "lpt64" : m == MAP_LPT32 ? "lpt32" : m == MAP_BLOCK ? "block" : "wave";
+}
 
 int64_t solid_reals(int p) { return (int64_t)p * (p + 1); }
 int64_t cost(const ListItem &it) { return (int64_t)it.p_in * it.p_in * it.p_in + (int64_t)it.p_out * it.p_out * it.p_out; }
@@ -165,6 +169,7 @@ hipError_t shfmm::launch_list_bin(const sh_ctx *ctx, bool f32, const ListBin &b,
     la.flags = flags & SH_ACCUMULATE;
     la.err = ctx->err_flag;
     if (b.mapping == MAP_GENERAL) return shfmm::launch_list_general(ctx->tabs, la, f32, b.wide, b.pmax, s);
+    if (b.mapping == MAP_BLOCK) return shfmm::launch_list_big(ctx->tabs, la, b.op, f32, b.pmax, s);
     return shfmm::launch_list_lpt(ctx->tabs, la, b.op, f32, b.bucket, s);
 }
 
@@ -499,6 +504,8 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         const int bk = lpt_bucket(pm);
         if (bk > 0)
             groups[std::make_tuple(0, it.op, bk, 0)].push_back(it);
+        else if (shfmm::big_available(it.p_in, it.p_out))
+            groups[std::make_tuple(2, it.op, pm <= 24 ? 24 : shfmm::kBigOrder - 1, 0)].push_back(it);
         else {
             const bool wide = f32 && pm >= shfmm::kF32WideOrder;
             groups[std::make_tuple(1, -1, general_class(pm), wide ? 1 : 0)].push_back(it);
@@ -515,6 +522,8 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         for (auto &x : v) b.pmax = std::max(b.pmax, std::max(x.p_in, x.p_out));
         if (std::get<0>(g.first) == 1) {
             b.mapping = MAP_GENERAL;
+        } else if (std::get<0>(g.first) == 2) {
+            b.mapping = MAP_BLOCK;
         } else {
             const int m = choose(b, v);
             if (m < 0) return SH_EDEVICE;
@@ -524,7 +533,7 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         b.item_count = (int64_t)v.size();
         list.insert(list.end(), v.begin(), v.end());
         std::vector<ListItem>().swap(v);
-        lay_out_bin(b, list, tasks, b.mapping == MAP_LPT32 ? 32 : 64);
+        lay_out_bin(b, list, tasks, b.mapping == MAP_LPT32 ? 32 : b.mapping == MAP_BLOCK ? 16 : 64);
         made.push_back(b);
     }
     // largest bins first, so that their persistent grids start first on the device
