@@ -13,7 +13,7 @@
 //     the 16 rotated solids, real and imaginary parts as two GEMMs sharing the fragments.
 // The O(P^2) steps (scaling, z-rotations) run on the VALU between the GEMMs, on the MFMA
 // output registers.  Rows (forward and backward rotations) and columns (z-step) are spread
-// over the 4 wavefronts in snake order; LDS barriers separate the phases.
+// over the 8 wavefronts (two per SIMD) in snake order; LDS barriers separate the phases.
 // FP64 16x16x4 MFMA operand layout (checked on the device): A[l % 16][l / 16],
 // B[l / 16][l % 16], D[4 j + l / 16][l % 16] for lane l and output register j.
 #include <hip/hip_runtime.h>
@@ -28,7 +28,9 @@ namespace shfmm {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kBT = 16;  // translations per block
+constexpr int kBT = 16;     // translations per block
+constexpr int kWaves = 8;   // wavefronts per workgroup (two per SIMD, to hide each other's latency)
+constexpr int kThreads = 64 * kWaves;
 
 template <typename Real>
 struct Pair2;
@@ -204,23 +206,23 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     }
     __syncthreads();
 
-    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Each thread issues 8
-    // loads before it uses any, so they are in flight together ----
+    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Each thread issues up to
+    // 16 loads before it uses any, so most of a block's loads are in flight together ----
     {
-        constexpr int U = 8;
+        constexpr int U = 16;
         const int total = PM * (PM + 1) / 2 * kBT;
-        for (int base = 0; base < total; base += 256 * U) {
+        for (int base = 0; base < total; base += kThreads * U) {
             R2 v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + 256 * u;
+                const int idx = base + tid + kThreads * u;
                 const int t = idx & 15, p = idx >> 4;
                 const int n = idx < total ? pair_degree(p) : PM;
                 v[u] = (n < p_in) ? *reinterpret_cast<const R2 *>(ain + L.ioff[t] + 2 * p) : R2{};
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + 256 * u;
+                const int idx = base + tid + kThreads * u;
                 if (idx >= total) continue;
                 const int t = idx & 15, p = idx >> 4;
                 const int n = pair_degree(p), m = p - n * (n + 1) / 2;
@@ -245,13 +247,13 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // ---- forward rotation, rows in snake order over the wavefronts; the next row's
     // fragments are fetched while the current row is transformed ----
     {
-        auto row_of = [&](int n0) { return n0 + (((n0 >> 2) & 1) ? 3 - wave : wave); };
+        auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         RowFrag cur, nxt;
         if (row_of(0) < p_in) load_row_frag(Ffw, row_of(0), lane, cur);
-        for (int n0 = 0; n0 < p_in; n0 += 4) {
+        for (int n0 = 0; n0 < p_in; n0 += kWaves) {
             const int n = row_of(n0);
             if (n >= p_in) break;
-            const int nn = row_of(n0 + 4);
+            const int nn = row_of(n0 + kWaves);
             if (nn < p_in) load_row_frag(Ffw, nn, lane, nxt);
             d4 D[2][2];
             swap_row(cur, X, n, lane, D);
@@ -263,15 +265,29 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     }
     __syncthreads();
 
-    // ---- z-translation, columns in snake order ----
+    // ---- z-translation, columns in snake order; the next column's fragments are fetched
+    // while the current column is multiplied ----
     {
         const double *Zt = tab.bz[basis][OP];
         const int t = lane & 15, kg = lane >> 4;
-        for (int m0 = 0; m0 < p_out; m0 += 4) {
-            const int m = m0 + (((m0 >> 2) & 1) ? 3 - wave : wave);
-            if (m >= p_out) continue;
+        auto col_of = [&](int m0) { return m0 + (((m0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
+        auto load_z = [&](int m, double (&za)[2][8]) {
             const double *Z = Zt + big_z_off(m);
-            const int kz = big_kz(m);
+            const int kz = big_kz(m), mto = (p_out - m + 15) / 16;
+            const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    za[mt][ks] = (mt < mto && ks < ki) ? Z[(mt * kz + ks) * 64 + lane] : 0.0;
+        };
+        double zcur[2][8], znxt[2][8];
+        if (col_of(0) < p_out) load_z(col_of(0), zcur);
+        for (int m0 = 0; m0 < p_out; m0 += kWaves) {
+            const int m = col_of(m0);
+            if (m >= p_out) break;
+            const int mn = col_of(m0 + kWaves);
+            if (mn < p_out) load_z(mn, znxt);
             const int mto = (p_out - m + 15) / 16;
             const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
             double b[2][8];
@@ -282,12 +298,6 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
                     const int i = m + 4 * ks + kg;
                     b[q][ks] = (ks < ki && i < p_in) ? X[(pos(i, m) + q) * kBT + t] : 0.0;
                 }
-            double za[2][8];
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks)
-                    za[mt][ks] = (mt < mto && ks < ki) ? Z[(mt * kz + ks) * 64 + lane] : 0.0;
             d4 res[2][2];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
@@ -296,8 +306,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 #pragma unroll
                     for (int ks = 0; ks < 8; ++ks) {
                         if (ks >= ki) break;
-                        a0 = mfma64(za[mt][ks], b[0][ks], a0);
-                        a1 = mfma64(za[mt][ks], b[1][ks], a1);
+                        a0 = mfma64(zcur[mt][ks], b[0][ks], a0);
+                        a1 = mfma64(zcur[mt][ks], b[1][ks], a1);
                     }
                 }
                 res[0][mt] = a0;
@@ -314,19 +324,23 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
                     X[(pos(o, m) + 1) * kBT + t] = m ? res[1][mt][j] : 0.0;
                 }
             }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) zcur[mt][ks] = znxt[mt][ks];
         }
     }
     __syncthreads();
 
     // ---- backward rotation, unscale ----
     {
-        auto row_of = [&](int n0) { return n0 + (((n0 >> 2) & 1) ? 3 - wave : wave); };
+        auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         RowFrag cur, nxt;
         if (row_of(0) < p_out) load_row_frag(Fbw, row_of(0), lane, cur);
-        for (int n0 = 0; n0 < p_out; n0 += 4) {
+        for (int n0 = 0; n0 < p_out; n0 += kWaves) {
             const int n = row_of(n0);
             if (n >= p_out) break;
-            const int nn = row_of(n0 + 4);
+            const int nn = row_of(n0 + kWaves);
             if (nn < p_out) load_row_frag(Fbw, nn, lane, nxt);
             d4 D[2][2];
             swap_row(cur, X, n, lane, D);
@@ -341,7 +355,7 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // ---- store ----
     {
         const int npair = p_out * (p_out + 1) / 2;
-        for (int idx = tid; idx < npair * kBT; idx += 256) {
+        for (int idx = tid; idx < npair * kBT; idx += kThreads) {
             const int t = idx & 15, p = idx >> 4;
             if (t >= nt) continue;
             const int n = pair_degree(p), m = p - n * (n + 1) / 2;
@@ -375,7 +389,7 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 
 // Batched form: translation i = 16 b + t of the call.
 template <typename Real, int OP, bool IDX>
-__global__ __launch_bounds__(256) void k_big(DevTables tab, TransArgs a)
+__global__ __launch_bounds__(kThreads) void k_big(DevTables tab, TransArgs a)
 {
     extern __shared__ double sm[];
     const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
@@ -410,10 +424,10 @@ hipError_t launch_big_one(const DevTables &tab, const TransArgs &a, hipStream_t 
     const void *fn = reinterpret_cast<const void *>(&k_big<Real, OP, IDX>);
     int dev = 0, cu = 256, occ = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, smem) != hipSuccess || occ < 1) occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, smem) != hipSuccess || occ < 1) occ = 1;
     const int64_t nblk = (a.count + kBT - 1) / kBT;
     const int64_t res = (int64_t)cu * occ;
-    const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(256);
+    const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(kThreads);
     hipLaunchKernelGGL((k_big<Real, OP, IDX>), grid, block, smem, s, tab, a);
     return hipGetLastError();
 }
@@ -429,7 +443,7 @@ hipError_t launch_big_op(const DevTables &tab, const TransArgs &a, hipStream_t s
 // Work-list form: one task (up to 16 items of one operation sharing (p_in, p_out)) per
 // workgroup pass; the LDS is sized for the bin's largest order.
 template <typename Real, int OP>
-__global__ __launch_bounds__(256) void k_big_list(DevTables tab, ListArgs la)
+__global__ __launch_bounds__(kThreads) void k_big_list(DevTables tab, ListArgs la)
 {
     extern __shared__ double sm[];
     const Real *ain = reinterpret_cast<const Real *>(la.arena_in);
@@ -459,9 +473,9 @@ hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pma
     const void *fn = reinterpret_cast<const void *>(&k_big_list<Real, OP>);
     int dev = 0, cu = 256, occ = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, smem) != hipSuccess || occ < 1) occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, smem) != hipSuccess || occ < 1) occ = 1;
     const int64_t res = (int64_t)cu * occ;
-    const dim3 grid((unsigned)(la.ntasks < res ? la.ntasks : res)), block(256);
+    const dim3 grid((unsigned)(la.ntasks < res ? la.ntasks : res)), block(kThreads);
     hipLaunchKernelGGL((k_big_list<Real, OP>), grid, block, smem, s, tab, la);
     return hipGetLastError();
 }

@@ -505,7 +505,7 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         if (bk > 0)
             groups[std::make_tuple(0, it.op, bk, 0)].push_back(it);
         else if (shfmm::big_available(it.p_in, it.p_out))
-            groups[std::make_tuple(2, it.op, pm <= 24 ? 24 : shfmm::kBigOrder - 1, 0)].push_back(it);
+            groups[std::make_tuple(2, it.op, pm <= 20 ? 20 : pm <= 24 ? 24 : shfmm::kBigOrder - 1, 0)].push_back(it);
         else {
             const bool wide = f32 && pm >= shfmm::kF32WideOrder;
             groups[std::make_tuple(1, -1, general_class(pm), wide ? 1 : 0)].push_back(it);
