@@ -32,14 +32,14 @@ __device__ __forceinline__ void static_for(F &&f)
 }
 
 // Greedy static schedule: items (rows or columns) sorted by cost, each given to the
-// least-loaded of the 4 wavefronts.  cost(i) ~ (i+1)^2 for rows, (P-m)^2 for columns.
-constexpr int row_owner(int P, int n)
+// least-loaded of the NW wavefronts.  cost(i) ~ (i+1)^2 for rows, (P-m)^2 for columns.
+constexpr int row_owner(int P, int n, int NW = 4)
 {
-    long load[4] = {0, 0, 0, 0};
+    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int own = 0;
     for (int k = P - 1; k >= 0; --k) {
         int w = 0;
-        for (int j = 1; j < 4; ++j)
+        for (int j = 1; j < NW; ++j)
             if (load[j] < load[w]) w = j;
         load[w] += (long)(k + 1) * (k + 1);
         if (k == n) own = w;
@@ -47,14 +47,14 @@ constexpr int row_owner(int P, int n)
     return own;
 }
 
-constexpr int col_owner(int PIN, int POUT, int m)
+constexpr int col_owner(int PIN, int POUT, int m, int NW = 4)
 {
-    long load[4] = {0, 0, 0, 0};
+    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int own = 0;
     const int PM = PIN > POUT ? PIN : POUT;
     for (int k = 0; k < PM; ++k) {
         int w = 0;
-        for (int j = 1; j < 4; ++j)
+        for (int j = 1; j < NW; ++j)
             if (load[j] < load[w]) w = j;
         const long ci = PIN - k > 0 ? PIN - k : 1;
         load[w] += ci * (POUT - k > 0 ? POUT - k : 1);
@@ -246,7 +246,7 @@ __device__ __forceinline__ void swap_row(cptr<Acc> T, const Acc (&xr)[N + 1], co
 
 // Calls f(std::integral_constant<int, W>) for the wavefront index W = wave, so that each
 // wavefront runs straight-line code for its own share of rows / columns.
-template <typename F>
+template <int NW = 4, typename F>
 __device__ __forceinline__ void per_wave(int wave, F &&f)
 {
     if (wave == 0)
@@ -255,8 +255,18 @@ __device__ __forceinline__ void per_wave(int wave, F &&f)
         f(std::integral_constant<int, 1>{});
     else if (wave == 2)
         f(std::integral_constant<int, 2>{});
-    else
+    else if (NW == 4 || wave == 3)
         f(std::integral_constant<int, 3>{});
+    else if constexpr (NW == 8) {
+        if (wave == 4)
+            f(std::integral_constant<int, 4>{});
+        else if (wave == 5)
+            f(std::integral_constant<int, 5>{});
+        else if (wave == 6)
+            f(std::integral_constant<int, 6>{});
+        else
+            f(std::integral_constant<int, 7>{});
+    }
 }
 
 template <typename Acc>
@@ -289,6 +299,18 @@ constexpr int lpt_min_waves()
 {
     return lpt_blocks_per_cu<Acc, PM>() >= 2 ? 2 : 1;
 }
+// wavefronts per workgroup: 8 (two per SIMD, to hide each other's latency) where LDS allows
+// only one workgroup per CU, else 4
+template <typename Acc, int PM>
+constexpr int lpt_waves()
+{
+    return lpt_blocks_per_cu<Acc, PM>() >= 2 ? 4 : 8;
+}
+template <typename Acc, int PM>
+constexpr int lpt_min_waves_nw()
+{
+    return lpt_blocks_per_cu<Acc, PM>() >= 2 || lpt_waves<Acc, PM>() == 8 ? 2 : 1;
+}
 template <typename Acc, int PM>
 constexpr bool lpt_hold_powers()
 {
@@ -298,13 +320,16 @@ constexpr bool lpt_hold_powers()
 // IDX: translations gather their input from the index array src and scatter to dst
 // (indexed pools); otherwise translation i of the call uses solid i of in / out.
 template <typename Real, typename Acc, int OP, int PIN, int POUT, bool IDX>
-__global__ __launch_bounds__(256, (lpt_min_waves<Acc, (PIN > POUT ? PIN : POUT)>()))
+__global__ __launch_bounds__((64 * lpt_waves<Acc, (PIN > POUT ? PIN : POUT)>()),
+                             (lpt_min_waves_nw<Acc, (PIN > POUT ? PIN : POUT)>()))
 void k_lpt(DevTables tab, TransArgs a)
 {
     constexpr int PM = PIN > POUT ? PIN : POUT;
     constexpr int SIN = PIN * (PIN + 1), SOUT = POUT * (POUT + 1);
     constexpr int SP = lpt_stride<PM>();
     constexpr bool HOLD = lpt_hold_powers<Acc, PM>();
+    constexpr int NW = lpt_waves<Acc, PM>();  // wavefronts of the workgroup
+    constexpr int NT = 64 * NW;               // its threads
     using P2 = typename Pair<Acc>::T;
     using R2 = typename Pair<Real>::T;
     __shared__ Acc X[64 * SP];
@@ -333,20 +358,20 @@ void k_lpt(DevTables tab, TransArgs a)
     // end of a partial block re-read a valid solid of the block -- so no load waits on
     // another (a guarded load splits the code and the wait-count pass then serialises).
     constexpr int NP = 64 * (SIN / 2);
-    constexpr int LIT = (NP + 255) / 256;
+    constexpr int LIT = (NP + NT - 1) / NT;
     constexpr bool PREFETCH = LIT * 2 * (int)sizeof(Real) / 4 <= 64;
     constexpr int CH = PREFETCH ? LIT : 16 * 4 / (int)sizeof(Real);  // loads per batch
     R2 pre[CH];
     Real prx = 0, pry = 0, prz = 1;
     const int64_t *__restrict__ gsrc = a.src;
     const int64_t *__restrict__ gdst = a.dst;
-    // issue the loads of pairs c0 + tid + 256 i (i < CH) of the block at bb (ntb translations)
+    // issue the loads of pairs c0 + tid + NT i (i < CH) of the block at bb (ntb translations)
     auto load_batch = [&](int64_t bb, int ntb, int c0) {
         int64_t row[IDX ? CH : 1];
         if constexpr (IDX) {
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                const int t = (c0 + tid + 256 * i) / (SIN / 2);
+                const int t = (c0 + tid + NT * i) / (SIN / 2);
                 row[i] = gsrc[bb + (t < ntb ? t : ntb - 1)];
             }
         }
@@ -355,7 +380,7 @@ void k_lpt(DevTables tab, TransArgs a)
         const int ldi = (int)a.ld_in;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const int p = c0 + tid + 256 * i;
+            const int p = c0 + tid + NT * i;
             const int t = p / (SIN / 2);
             const int k = 2 * (p - t * (SIN / 2));
             if constexpr (IDX)
@@ -368,8 +393,8 @@ void k_lpt(DevTables tab, TransArgs a)
     auto store_batch_lds = [&](int c0) {
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const int p = c0 + tid + 256 * i;
-            if (c0 + 256 * i + 256 <= NP || p < NP) {
+            const int p = c0 + tid + NT * i;
+            if (c0 + NT * i + NT <= NP || p < NP) {
                 const int t = p / (SIN / 2);
                 const int k = 2 * (p - t * (SIN / 2));
                 *reinterpret_cast<P2 *>(&X[t * SP + k]) = P2{(Acc)pre[i].x, (Acc)pre[i].y};
@@ -396,7 +421,7 @@ void k_lpt(DevTables tab, TransArgs a)
             store_batch_lds(0);
         } else {
 #pragma unroll 1
-            for (int c0 = 0; c0 < NP; c0 += 256 * CH) {
+            for (int c0 = 0; c0 < NP; c0 += NT * CH) {
                 load_batch(base, nt, c0);
                 store_batch_lds(c0);
             }
@@ -432,10 +457,10 @@ void k_lpt(DevTables tab, TransArgs a)
         }
 
         // ---- forward rotation of the input rows ----
-        per_wave(wave, [&](auto wc) {
+        per_wave<NW>(wave, [&](auto wc) {
         static_for<0, PIN>([&](auto nc) {
             constexpr int n = decltype(nc)::value;
-            if constexpr (row_owner(PIN, n) == decltype(wc)::value) {
+            if constexpr (row_owner(PIN, n, NW) == decltype(wc)::value) {
             Acc xr[n + 1], xi[n + 1], yr[n + 1], yi[n + 1];
 #pragma unroll
             for (int m = 0; m <= n; ++m) {
@@ -462,10 +487,10 @@ void k_lpt(DevTables tab, TransArgs a)
         lds_barrier();
 
         // ---- z-axis step, one column (order m) at a time, unit shift ----
-        per_wave(wave, [&](auto wc) {
+        per_wave<NW>(wave, [&](auto wc) {
         static_for<0, POUT>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            if constexpr (col_owner(PIN, POUT, m) != decltype(wc)::value) {
+            if constexpr (col_owner(PIN, POUT, m, NW) != decltype(wc)::value) {
             } else if constexpr (m >= PIN) {
 #pragma unroll
                 for (int o = m; o < POUT; ++o) *reinterpret_cast<P2 *>(&Xt[solid_pos(o, m)]) = P2{(Acc)0, (Acc)0};
@@ -497,10 +522,10 @@ void k_lpt(DevTables tab, TransArgs a)
         lds_barrier();
 
         // ---- backward rotation of the output rows ----
-        per_wave(wave, [&](auto wc) {
+        per_wave<NW>(wave, [&](auto wc) {
         static_for<0, POUT>([&](auto nc) {
             constexpr int n = decltype(nc)::value;
-            if constexpr (row_owner(POUT, n) == decltype(wc)::value) {
+            if constexpr (row_owner(POUT, n, NW) == decltype(wc)::value) {
             Acc xr[n + 1], xi[n + 1], yr[n + 1], yi[n + 1];
 #pragma unroll
             for (int m = 0; m <= n; ++m) {
@@ -527,7 +552,7 @@ void k_lpt(DevTables tab, TransArgs a)
         //      shifts take the per-element path below. ----
         if (!acc && !bad_any) {
             constexpr int NQ = 64 * (SOUT / 2);
-            constexpr int SIT = (NQ + 255) / 256;
+            constexpr int SIT = (NQ + NT - 1) / NT;
             const int nq = nt * (SOUT / 2);
             int64_t drow[IDX ? SIT : 1];
             Real *__restrict__ bout = gout + base * a.ld_out;  // block base + 32-bit offsets
@@ -535,15 +560,15 @@ void k_lpt(DevTables tab, TransArgs a)
             if constexpr (IDX) {
 #pragma unroll
                 for (int i = 0; i < SIT; ++i) {
-                    const int t = (tid + 256 * i) / (SOUT / 2);
+                    const int t = (tid + NT * i) / (SOUT / 2);
                     drow[i] = gdst[base + (t < nt ? t : nt - 1)];
                 }
             }
             if (nt == 64) {
 #pragma unroll
                 for (int i = 0; i < SIT; ++i) {
-                    const int p = tid + 256 * i;
-                    if (256 * i + 256 <= NQ || p < NQ) {
+                    const int p = tid + NT * i;
+                    if (NT * i + NT <= NQ || p < NQ) {
                         const int t = p / (SOUT / 2);
                         const int k = 2 * (p - t * (SOUT / 2));
                         const P2 v = *reinterpret_cast<const P2 *>(&X[t * SP + k]);
@@ -554,7 +579,7 @@ void k_lpt(DevTables tab, TransArgs a)
             } else {
 #pragma unroll
                 for (int i = 0; i < SIT; ++i) {
-                    const int p = tid + 256 * i;
+                    const int p = tid + NT * i;
                     if (p < nq) {
                         const int t = p / (SOUT / 2);
                         const int k = 2 * (p - t * (SOUT / 2));
@@ -565,7 +590,7 @@ void k_lpt(DevTables tab, TransArgs a)
                 }
             }
         } else
-        for (int p = tid; p < nt * (SOUT / 2); p += 256) {
+        for (int p = tid; p < nt * (SOUT / 2); p += NT) {
             const int t = p / (SOUT / 2);
             const int k = 2 * (p - t * (SOUT / 2));
             const int64_t di = IDX ? gdst[base + t] : base + t;
@@ -611,7 +636,7 @@ hipError_t launch_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
     const void *fn = reinterpret_cast<const void *>(&k_lpt<Real, Acc, OP, PV, PV, IDX>);
     const int64_t nblk = (a.count + 63) / 64;
     const int64_t res = resident_workgroups(fn);
-    const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(256);
+    const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(64 * lpt_waves<Acc, PV>());
     hipLaunchKernelGGL((k_lpt<Real, Acc, OP, PV, PV, IDX>), grid, block, 0, s, tab, a);
     return hipGetLastError();
 }
