@@ -177,17 +177,20 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
     res["rot_f32_err_max"], res["rot_f32_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
     bpt = bytes_per_translation(P, P, 4) - 12  # FP32 solids in and out, no shift array
-    for prec, name in ((sh.SH_SHARED_BF16X6, "bf16x6"), (sh.SH_SHARED_BF16X3, "bf16x3")):
+    for prec, name in ((sh.SH_SHARED_BF16X6, "bf16x6"), (sh.SH_SHARED_BF16X3, "bf16x3"), (sh.SH_SHARED_FP32, "fp32mfma")):
         t0 = time.perf_counter()
         op = sh.Shared(ctx, "m2l", P, P, offs, prec)
         res[f"{name}_build_s"] = round(time.perf_counter() - t0, 3)
         res[f"{name}_operator_bytes"] = op.nbytes()
         d_L32.zero_()
         t = time_launch(torch, lambda: op.execute(n, d_cs, d_M32, S, d_L32, S), reps)
-        products = 6 if prec == sh.SH_SHARED_BF16X6 else 3
         res[f"{name}_per_s"] = n / t
         res[f"{name}_ms"] = round(t * 1e3, 4)
-        res[f"{name}_frac_mfma_bf16"] = 2.0 * S * S * products * n / t / 2.5e15
+        if prec == sh.SH_SHARED_FP32:
+            res[f"{name}_frac_mfma_fp32"] = 2.0 * S * S * n / t / 157.3e12
+        else:
+            products = 6 if prec == sh.SH_SHARED_BF16X6 else 3
+            res[f"{name}_frac_mfma_bf16"] = 2.0 * S * S * products * n / t / 2.5e15
         res[f"{name}_frac_hbm"] = bpt * n / t / 1e9 / HBM_PEAK_GBS
         e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
         res[f"{name}_err_max"], res[f"{name}_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
@@ -197,27 +200,29 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     return res
 
 
-def run_serving(sh, ctx, torch, dev, seconds=5.0, rate=200.0, n_slots=200_000):
+def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, staging=10 << 20):
     """The serving workload: a Poisson stream (mean `rate` jobs/s, for `seconds`) of jobs of
     10^3..10^5 translations (log-uniform), one order P in {4, 8, 16, 24, 30} and one dtype
     (FP32 or FP64) per job, on resident trees (one per order and dtype, n_slots multipoles and
     locals each).  Operations M2M / M2L / L2L with probabilities 0.2 / 0.6 / 0.2; M2M and L2L
-    read the first half of a pool and write the second.  Latency: submission to completion."""
+    read the first half of a pool and write the second.  The staging budget (admission by
+    footprint, 80 B per translation) holds one of the largest jobs (8 MB), so admission defers
+    jobs under bursts.  Latency: submission to completion."""
     from paper_2202_02847_amd import workloads as wl
 
     orders = [4, 8, 16, 24, 30]
     dts = [sh.SH_F64, sh.SH_F32]
     pool = sum(2 * n_slots * P * (P + 1) * (8 if dt == sh.SH_F64 else 4) for P in orders for dt in dts)
-    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=512 << 20, streams=4, max_batch_jobs=64)
+    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=staging, streams=4, max_batch_jobs=64)
     trees = {}
     for P in orders:
         for dt in dts:
             t = srv.tree_create(dt, P, n_slots, P, n_slots)
             npdt = np.float64 if dt == sh.SH_F64 else np.float32
-            block = np.random.default_rng(P).normal(size=(1000, P * (P + 1))).astype(npdt) * 1e-2
+            block = np.random.default_rng(P).normal(size=(1024, P * (P + 1))).astype(npdt) * 1e-2
             for pool_id in (0, 1):
-                for first in range(0, n_slots, 1000):
-                    srv.tree_write(t, pool_id, first, block)
+                for first in range(0, n_slots, 1024):
+                    srv.tree_write(t, pool_id, first, block[: min(1024, n_slots - first)])
             trees[(P, dt)] = t
     rng = wl.rng_for(5, 0)
     ops = ["m2m", "m2l", "l2l"]
@@ -226,7 +231,9 @@ def run_serving(sh, ctx, torch, dev, seconds=5.0, rate=200.0, n_slots=200_000):
     ids = []
     log(f"[bench] serving {len(arrivals)} jobs over {seconds:.0f} s")
     t0 = time.perf_counter()
-    for a in arrivals:
+    for k, a in enumerate(arrivals):
+        if k and k % 2000 == 0:
+            log(f"[bench] serving: {k} jobs submitted")
         P = orders[rng.integers(len(orders))]
         dt = dts[rng.integers(2)]
         op = ops[rng.choice(3, p=[0.2, 0.6, 0.2])]
@@ -253,7 +260,8 @@ def run_serving(sh, ctx, torch, dev, seconds=5.0, rate=200.0, n_slots=200_000):
             "translations_per_s": st["translations_done"] / max(st["elapsed_s"], 1e-9),
             "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
             "max_ms": round(st["max_s"] * 1e3, 3), "mean_batch_jobs": round(st["mean_batch_jobs"], 2),
-            "batches": st["batches"], "queue_peak": st["queue_peak"],
+            "batches": st["batches"], "queue_peak": st["queue_peak"], "jobs_deferred": st["jobs_deferred"],
+            "staging_budget_mb": round(staging / 2 ** 20, 1),
             "staging_peak_mb": round(st["staging_peak_bytes"] / 2 ** 20, 1)}
 
 
@@ -304,9 +312,19 @@ def cpu_baseline(seconds_target=10.0):
                 break
     except OSError:
         pass
+    by_order = {}
+    for PP, nn in ((16, 1 << 14), (30, 1 << 12)):
+        cc = wl.config2(n_m2l=nn, n_child=8, P=PP)
+        MM = o.p2m_batch(PP, np.zeros((nn, 3)), cc["pts"], cc["q"], nthreads=threads)
+        t0 = time.perf_counter()
+        o.translate_batch("m2l", PP, PP, cc["r_m2l"], MM, nthreads=threads)
+        tt = time.perf_counter() - t0
+        by_order[f"P{PP}"] = {"translations": nn, "seconds": round(tt, 3), "per_s": nn / tt,
+                              "per_s_per_core": nn / tt / threads}
     return {"value": n / dt, "unit": "translations/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} M2L at P=10 FP64 (octree shifts, 32-point multipoles), "
-                      f"double-height O(P^4) sum, OpenMP over {threads} threads, {dt:.1f} s; {cpu}"}
+                      f"double-height O(P^4) sum, OpenMP over {threads} threads, {dt:.1f} s; {cpu}",
+            "per_core": n / dt / threads, "by_order": by_order}
 
 
 def run_counters(sh, ctx, torch, dev, P, steps):
@@ -334,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip P=16/30, FP32 and naive extras")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=50.0,
+                    help="length of the serving workload's Poisson stream (200 jobs/s)")
     ap.add_argument("--counters", type=int, default=0, metavar="P",
                     help="counter-collection mode: one 1 GiB copy (the reference kernel for "
                          "FETCH_SIZE/WRITE_SIZE scaling), then --steps launches of the octree M2L "
@@ -402,6 +422,13 @@ def main():
              "all_translations_per_s": (n + 2 * nc) / (ms_step / 1e3)}
 
     if not args.no_extra:
+        # device copy bandwidth (read + write) of a 2 GiB buffer, as measured context for the peak
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        t = time_launch(torch, lambda: dst.copy_(src), 5)
+        extra["copy_gbs"] = round(2 * src.numel() * 8 / t / 1e9, 1)
+        del src, dst
+        torch.cuda.empty_cache()
         # FP32 (normalised basis) at P=10 on the same multipoles
         w = norm_weights(sh, torch, dev, P, 0)
         d_M32 = (d_M * w).float()
@@ -417,7 +444,7 @@ def main():
         del d_M, d_L, d_M2, d_L2, I
         torch.cuda.empty_cache()
         log("[bench] serving")
-        extra["serving"] = run_serving(sh, ctx, torch, dev)
+        extra["serving"] = run_serving(sh, ctx, torch, dev, seconds=args.serve_seconds)
         torch.cuda.empty_cache()
         log("[bench] shared-direction precision forms P=16")
         extra["precision_p16"] = run_precision(sh, ctx, torch, dev)

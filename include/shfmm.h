@@ -207,10 +207,12 @@ sh_status sh_translate_list(sh_ctx *ctx, int dtype, const sh_item *items, int64_
  * them to FP32 normalised-basis solids as a grouped GEMM on MFMA with FP32 accumulation:
  *   SH_SHARED_BF16X3: a_hi b_hi + a_hi b_mid + a_mid b_hi (about 16 significant bits;
  *                     per-degree error ~1e-5 .. 1e-4);
- *   SH_SHARED_BF16X6: adds a_hi b_lo + a_mid b_mid + a_lo b_hi (about FP32: ~1e-6).
+ *   SH_SHARED_BF16X6: adds a_hi b_lo + a_mid b_mid + a_lo b_hi (about FP32: ~1e-6);
+ *   SH_SHARED_FP32:   FP32 operands (the operator rounded once from FP64) on the FP32 MFMA.
  * The FP32 solids use the layout and normalised basis of the FP32 batched calls. */
 typedef struct sh_shared sh_shared;
 
+#define SH_SHARED_FP32 1
 #define SH_SHARED_BF16X3 3
 #define SH_SHARED_BF16X6 6
 
@@ -273,6 +275,7 @@ typedef struct sh_job {
 typedef struct sh_server_stats {
     int64_t jobs_done, jobs_failed, translations_done, batches, queue_peak;
     int64_t staging_peak_bytes, pool_used_bytes;
+    int64_t jobs_deferred;  /* jobs passed over at least once because staging was full */
     double mean_batch_jobs;
     double elapsed_s;       /* first submission to last completion */
     double p50_s, p99_s, mean_s, max_s;  /* job latency: submission to completion */

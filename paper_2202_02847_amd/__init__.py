@@ -24,6 +24,7 @@ SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
 SH_PLAN_AUTOTUNE = 2
 SH_PLAN_NO_GRAPH = 4
+SH_SHARED_FP32 = 1
 SH_SHARED_BF16X3 = 3
 SH_SHARED_BF16X6 = 6
 SH_MAX_ORDER = 64
@@ -423,7 +424,8 @@ class Job(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("jobs_done", "jobs_failed", "translations_done", "batches",
-                                              "queue_peak", "staging_peak_bytes", "pool_used_bytes")] + \
+                                              "queue_peak", "staging_peak_bytes", "pool_used_bytes",
+                                              "jobs_deferred")] + \
                [(n, ctypes.c_double) for n in ("mean_batch_jobs", "elapsed_s", "p50_s", "p99_s", "mean_s", "max_s")]
 
     def as_dict(self):

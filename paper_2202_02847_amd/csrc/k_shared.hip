@@ -78,6 +78,31 @@ __global__ void k_shared_prep(const double *__restrict__ traw, int64_t nclass, i
     }
 }
 
+// FP32 operator fragments for the 16x16x4 FP32 MFMA: frag[c][nt][ks][lane][j] holds B[k][n]
+// with k = 32 ks + 4 j + lane / 16 and n = 16 nt + lane % 16 (a lane's 8 values of a 32-wide K
+// block are contiguous), rounded once from the FP64 image.
+__global__ void k_shared_prep_f32(const double *__restrict__ traw, int64_t nclass, int K, int N, int KS, int NT,
+                                  const double *__restrict__ s_in, const double *__restrict__ s_out,
+                                  float *__restrict__ frag)
+{
+    const int64_t per_class = (int64_t)NT * KS * 512;
+    const int64_t total = nclass * per_class;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / per_class;
+        int64_t rest = e - c * per_class;
+        const int j = (int)(rest & 7);
+        const int lane = (int)((rest >> 3) & 63);
+        rest >>= 9;
+        const int ks = (int)(rest % KS);
+        const int nt = (int)(rest / KS);
+        const int k = 32 * ks + 4 * j + (lane >> 4);
+        const int n = 16 * nt + (lane & 15);
+        double t = 0.0;
+        if (k < K && n < N) t = traw[(c * K + k) * N + n] * s_out[n] / s_in[k];
+        frag[e] = (float)t;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Grouped GEMM.  Work item = (class c, 64 consecutive translations of c, a chunk of up to
 // 20 output tiles of 16).  The FP32 input rows of the 64 translations are split into BF16
@@ -146,7 +171,8 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
         const int rows = (int)((s1 - first) < kTM ? (s1 - first) : kTM);
         const int nt0 = chunk * kNTC;
         // this wave's output tiles (tiles past the end re-read the last one; not stored)
-        const unsigned short *bbase = a.frag + (int64_t)c * NPB * a.frag_class_stride + lane * 8;
+        const unsigned short *bbase =
+            reinterpret_cast<const unsigned short *>(a.frag) + (int64_t)c * NPB * a.frag_class_stride + lane * 8;
         int toff[kNTW];  // wave-uniform offsets of this wave's output tiles
 #pragma unroll
         for (int i = 0; i < kNTW; ++i) {
@@ -279,7 +305,150 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
     }
 }
 
+// FP32 form of the grouped GEMM (v_mfma_f32_16x16x4f32, FP32 operands and accumulation): the
+// same work items and walk as above; inputs staged in LDS as FP32 with each lane's 8 values of
+// a 32-wide K block contiguous (As[t][ks][g][j], k = 32 ks + 4 j + g).
+__global__ __launch_bounds__(256, 2) void k_shared_gemm_f32(SharedArgs a)
+{
+    constexpr int KB = kKC / 32;  // 32-wide K blocks per LDS chunk
+    __shared__ float As[kTM][KB][4][8 + 1];  // row padded so that lanes of one row avoid a bank
+    __shared__ int tiles_before[kMaxClasses + 1];
+    __shared__ unsigned char live[kMaxK];
+    typedef float f8 __attribute__((ext_vector_type(8)));
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nclass = a.nclass;
+    const int64_t count = a.count;
+    const float *frag = reinterpret_cast<const float *>(a.frag);
+    for (int k = tid; k < a.Kp; k += 256) live[k] = a.live_in[k];
+    const int nchunks = (a.NT + kNTC - 1) / kNTC;
+    if (wave == 0) {
+        int carry = 0;
+        for (int c0 = 0; c0 < nclass; c0 += 64) {
+            const int c = c0 + lane;
+            int v = 0;
+            if (c < nclass) {
+                int64_t s0 = a.class_start[c], s1 = a.class_start[c + 1];
+                s0 = s0 < 0 ? 0 : (s0 > count ? count : s0);
+                s1 = s1 < s0 ? s0 : (s1 > count ? count : s1);
+                v = (int)((s1 - s0 + kTM - 1) / kTM) * nchunks;
+            }
+            for (int d = 1; d < 64; d <<= 1) {
+                const int u = __shfl_up(v, d);
+                if (lane >= d) v += u;
+            }
+            if (c < nclass) tiles_before[c + 1] = carry + v;
+            carry += __shfl(v, 63);
+        }
+        if (lane == 0) tiles_before[0] = 0;
+    }
+    __syncthreads();
+    const int total = tiles_before[nclass];
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
+    const int w_end = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    for (int w = (int)(((int64_t)total * xcd) >> 3) + slot; w < w_end; w += per_xcd) {
+        int lo = 0, hi = nclass - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tiles_before[mid] <= w) lo = mid; else hi = mid - 1;
+        }
+        const int c = lo;
+        const int local = w - tiles_before[c];
+        const int mtile = local / nchunks, chunk = local - mtile * nchunks;
+        int64_t s0 = a.class_start[c], s1 = a.class_start[c + 1];
+        s0 = s0 < 0 ? 0 : (s0 > count ? count : s0);
+        s1 = s1 < s0 ? s0 : (s1 > count ? count : s1);
+        const int64_t first = s0 + (int64_t)mtile * kTM;
+        const int rows = (int)((s1 - first) < kTM ? (s1 - first) : kTM);
+        const int nt0 = chunk * kNTC;
+        const float *bbase = frag + (int64_t)c * a.frag_class_stride + lane * 8;
+        int toff[kNTW];
+#pragma unroll
+        for (int i = 0; i < kNTW; ++i) {
+            const int nt = nt0 + wave + 4 * i;
+            const int ntc = nt < a.NT ? nt : a.NT - 1;
+            toff[i] = __builtin_amdgcn_readfirstlane(ntc * a.KS * 512);
+        }
+        const bool last_tile = nt0 + wave + 4 * (kNTW - 1) < a.NT;
+        f32x4 acc[4][kNTW];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int t = 0; t < kNTW; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < a.Kp; kc += kKC) {
+            const int kw = (a.Kp - kc) < kKC ? (a.Kp - kc) : kKC;
+            __syncthreads();
+            for (int p = tid; p < kTM * (kw / 2); p += 256) {
+                const int t = p / (kw / 2);
+                const int k = kc + 2 * (p - t * (kw / 2));
+                const int64_t row = first + (t < rows ? t : rows - 1);
+                float2 v = make_float2(0.f, 0.f);
+                if (k < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k);
+                const int r0 = k - kc, r1 = r0 + 1;
+                As[t][r0 >> 5][r0 & 3][(r0 & 31) >> 2] = live[k] ? v.x : 0.f;
+                As[t][r1 >> 5][r1 & 3][(r1 & 31) >> 2] = live[k + 1] ? v.y : 0.f;
+            }
+            __syncthreads();
+            for (int kb = 0; kb < kw / 32; ++kb) {
+                const int kglob = (kc >> 5) + kb;
+                f8 b[kNTW];
+#pragma unroll
+                for (int i = 0; i < kNTW; ++i) b[i] = *reinterpret_cast<const f8 *>(bbase + toff[i] + kglob * 512);
+                float av[4][8];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) av[mt][j] = As[mt * 16 + (lane & 15)][kb][lane >> 4][j];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int i = 0; i < kNTW - 1; ++i)
+                            acc[mt][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt][j], b[i][j], acc[mt][i], 0, 0, 0);
+                    if (last_tile) {
+#pragma unroll
+                        for (int mt = 0; mt < 4; ++mt)
+                            acc[mt][kNTW - 1] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt][j], b[kNTW - 1][j], acc[mt][kNTW - 1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        const bool accumulate = (a.flags & 1u) != 0;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+            for (int i = 0; i < kNTW; ++i) {
+                const int n = (nt0 + wave + 4 * i) * 16 + (lane & 15);
+                if (n >= a.N) continue;
+                const bool live_o = a.live_out[n] != 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t = mt * 16 + 4 * (lane >> 4) + j;
+                    if (t >= rows) continue;
+                    float *o = a.out + (first + t) * a.ld_out + n;
+                    float v = live_o ? acc[mt][i][j] : 0.f;
+                    if (accumulate && live_o) v += *o;
+                    *o = v;
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_shared_prep_f32(const double *traw, int64_t nclass, int K, int N, int KS, int NT,
+                                  const double *s_in, const double *s_out, float *frag, hipStream_t s)
+{
+    const int64_t total = nclass * (int64_t)NT * KS * 512;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_shared_prep_f32, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, traw,
+                       nclass, K, N, KS, NT, s_in, s_out, frag);
+    return hipGetLastError();
+}
 
 hipError_t launch_shared_prep(const double *traw, int64_t nclass, int K, int N, int KS, int NT, int npieces,
                               const double *s_in, const double *s_out, unsigned short *frag, hipStream_t s)
@@ -297,8 +466,9 @@ int shared_max_classes() { return kMaxClasses; }
 hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s)
 {
     if (a.count <= 0 || a.nclass <= 0) return hipSuccess;
-    const void *fn = prec == 6 ? reinterpret_cast<const void *>(&k_shared_gemm<6>)
-                               : reinterpret_cast<const void *>(&k_shared_gemm<3>);
+    const void *fn = prec == 6   ? reinterpret_cast<const void *>(&k_shared_gemm<6>)
+                     : prec == 3 ? reinterpret_cast<const void *>(&k_shared_gemm<3>)
+                                 : reinterpret_cast<const void *>(&k_shared_gemm_f32);
     const int res = lpt::resident_workgroups(fn);
     // enough work items for the whole batch, capped at the resident count (persistent loop)
     const int nchunks = (a.NT + kNTC - 1) / kNTC;
@@ -308,8 +478,10 @@ hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s)
     const dim3 grid((unsigned)g), block(256);
     if (prec == 6)
         hipLaunchKernelGGL(k_shared_gemm<6>, grid, block, 0, s, a);
-    else
+    else if (prec == 3)
         hipLaunchKernelGGL(k_shared_gemm<3>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(k_shared_gemm_f32, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ struct SharedArgs {
     int64_t ld_in;
     float *out;
     int64_t ld_out;
-    const unsigned short *frag;     // operator fragments (BF16 pieces)
+    const void *frag;               // operator fragments (BF16 pieces, or FP32 values)
     int64_t frag_class_stride;      // elements per (class, piece)
     const unsigned char *live_in;   // Kp flags: input real used (not Im C_n^0, not padding)
     const unsigned char *live_out;  // N flags: output real not Im C_n^0
@@ -85,6 +85,9 @@ struct SharedArgs {
 };
 hipError_t launch_shared_prep(const double *traw, int64_t nclass, int K, int N, int KS, int NT, int npieces,
                               const double *s_in, const double *s_out, unsigned short *frag, hipStream_t s);
+hipError_t launch_shared_prep_f32(const double *traw, int64_t nclass, int K, int N, int KS, int NT,
+                                  const double *s_in, const double *s_out, float *frag, hipStream_t s);
+// prec: 6 / 3 (BF16 split, frag = BF16 pieces) or 1 (FP32, frag = floats)
 hipError_t launch_shared_gemm(const SharedArgs &a, int prec, hipStream_t s);
 int shared_max_classes();
 

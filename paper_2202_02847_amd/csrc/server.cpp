@@ -109,6 +109,7 @@ struct Job {
     int64_t footprint = 0;
     double t_submit = 0, t_done = 0;
     bool done = false;
+    bool deferred = false;  // passed over at least once for lack of staging
     int status = SH_OK;
 };
 
@@ -150,6 +151,7 @@ struct sh_server {
     // statistics
     std::vector<double> latencies;
     int64_t jobs_done = 0, translations_done = 0, batches = 0, batch_jobs = 0, queue_peak = 0, failed = 0;
+    int64_t jobs_deferred = 0;
     double t_first_submit = -1, t_last_done = -1;
 
     int inflight_total() const
@@ -276,7 +278,14 @@ void scheduler_main(sh_server *S)
                 const Job &j = *S->jobs.at(S->queue[qi]);
                 Tree &t = S->trees.at(j.tree);
                 if (t.busy || std::find(claimed.begin(), claimed.end(), j.tree) != claimed.end()) continue;
-                if (need + j.footprint > free_total) continue;
+                if (need + j.footprint > free_total) {
+                    Job &jm = *S->jobs.at(S->queue[qi]);
+                    if (!jm.deferred) {
+                        jm.deferred = true;
+                        ++S->jobs_deferred;
+                    }
+                    continue;
+                }
                 need += j.footprint;
                 take.push_back(qi);
                 claimed.push_back(j.tree);
@@ -669,6 +678,7 @@ sh_status sh_server_stats_get(sh_server *S, sh_server_stats *st)
         st->batches = S->batches;
         st->mean_batch_jobs = S->batches ? (double)S->batch_jobs / (double)S->batches : 0.0;
         st->queue_peak = S->queue_peak;
+        st->jobs_deferred = S->jobs_deferred;
         st->staging_peak_bytes = S->stage_alloc.peak;
         st->pool_used_bytes = S->pool_alloc.used;
         st->elapsed_s = (S->t_first_submit >= 0 && S->t_last_done >= 0) ? S->t_last_done - S->t_first_submit : 0.0;

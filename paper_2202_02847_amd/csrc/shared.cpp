@@ -19,7 +19,7 @@ struct sh_shared {
     int op = 0, p_in = 0, p_out = 0, nclass = 0, prec = 0;
     int K = 0, Kp = 0, N = 0, NT = 0, KS = 0;
     void *mem = nullptr;
-    unsigned short *frag = nullptr;
+    void *frag = nullptr;  // BF16 pieces (x3, x6) or FP32 values
     unsigned char *live_in = nullptr, *live_out = nullptr;
     int64_t frag_class_stride = 0;
     ~sh_shared()
@@ -66,7 +66,7 @@ struct DevBuf {
 sh_status build(sh_shared *o, const double *shifts)
 {
     const int K = o->K, N = o->N;
-    const int np = o->prec == 6 ? 3 : 2;
+    const int np = o->prec == 6 ? 3 : o->prec == 3 ? 2 : 1;
     hipError_t e;
     // unit input solids (the K x K identity; the Im C_n^0 columns are ignored by the kernels)
     std::vector<double> eye((size_t)K * K, 0.0);
@@ -108,11 +108,17 @@ sh_status build(sh_shared *o, const double *shifts)
                                                d_src.as<int64_t>(), d_eye.p, K, d_dst.as<int64_t>(), d_raw.p, N, 0,
                                                nullptr);
         if (st != SH_OK) return st;
-        unsigned short *dst = o->frag + (int64_t)c0 * np * o->frag_class_stride;
-        if (shfmm::launch_shared_prep(d_raw.as<double>(), nc, K, N, o->KS, o->NT, np, d_sin.as<double>(),
-                                      d_sout.as<double>(), dst, nullptr) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess)
-            return SH_EDEVICE;
+        hipError_t pe;
+        if (o->prec == SH_SHARED_FP32) {
+            float *dst = static_cast<float *>(o->frag) + (int64_t)c0 * o->frag_class_stride;
+            pe = shfmm::launch_shared_prep_f32(d_raw.as<double>(), nc, K, N, o->KS, o->NT, d_sin.as<double>(),
+                                               d_sout.as<double>(), dst, nullptr);
+        } else {
+            unsigned short *dst = static_cast<unsigned short *>(o->frag) + (int64_t)c0 * np * o->frag_class_stride;
+            pe = shfmm::launch_shared_prep(d_raw.as<double>(), nc, K, N, o->KS, o->NT, np, d_sin.as<double>(),
+                                           d_sout.as<double>(), dst, nullptr);
+        }
+        if (pe != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SH_EDEVICE;
     }
     return SH_OK;
 }
@@ -127,7 +133,8 @@ sh_status sh_shared_create(sh_ctx *ctx, int op, int p_in, int p_out, int nclass,
     if (!out) return SH_EINVAL;
     *out = nullptr;
     if (!ctx || !shifts || (op != SH_M2M && op != SH_M2L && op != SH_L2L) ||
-        (precision != SH_SHARED_BF16X3 && precision != SH_SHARED_BF16X6) || nclass < 1 ||
+        (precision != SH_SHARED_BF16X3 && precision != SH_SHARED_BF16X6 && precision != SH_SHARED_FP32) ||
+        nclass < 1 ||
         nclass > shfmm::shared_max_classes())
         return SH_EINVAL;
     if (p_in < 1 || p_out < 1 || p_in > ctx->max_order || p_out > ctx->max_order) return SH_EORDER;
@@ -152,15 +159,17 @@ sh_status sh_shared_create(sh_ctx *ctx, int op, int p_in, int p_out, int nclass,
         o->NT = (o->N + 15) / 16;
         o->KS = o->Kp / 32;
         o->frag_class_stride = (int64_t)o->NT * o->KS * 512;
-        const int np = precision == SH_SHARED_BF16X6 ? 3 : 2;
-        const size_t fb = (size_t)nclass * np * o->frag_class_stride * 2;
+        // BF16 pieces (2 bytes, 3 or 2 per entry) or one FP32 value
+        const size_t fb = precision == SH_SHARED_FP32 ? (size_t)nclass * o->frag_class_stride * 4
+                                                      : (size_t)nclass * (precision == SH_SHARED_BF16X6 ? 3 : 2) *
+                                                            o->frag_class_stride * 2;
         const size_t fa = (fb + 255) & ~size_t(255);
         if (hipMalloc(&o->mem, fa + (size_t)o->Kp + (size_t)o->N) != hipSuccess) {
             o->mem = nullptr;
             delete o;
             return SH_ENOMEM;
         }
-        o->frag = reinterpret_cast<unsigned short *>(o->mem);
+        o->frag = o->mem;
         o->live_in = reinterpret_cast<unsigned char *>(o->mem) + fa;
         o->live_out = o->live_in + o->Kp;
         std::vector<unsigned char> li((size_t)o->Kp), lo((size_t)o->N);
@@ -224,6 +233,7 @@ sh_status sh_shared_execute(const sh_shared *o, int64_t count, const int64_t *cl
 int64_t sh_shared_bytes(const sh_shared *o)
 {
     if (!o) return -1;
+    if (o->prec == SH_SHARED_FP32) return (int64_t)o->nclass * o->frag_class_stride * 4;
     const int np = o->prec == SH_SHARED_BF16X6 ? 3 : 2;
     return (int64_t)o->nclass * np * o->frag_class_stride * 2;
 }
