@@ -87,29 +87,31 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
 }
 
 // Operator fragments of row n (both parities and parts, every K step; K steps past the
-// row's count are never used).  Both swaps of a row use the same table.
+// row's count are zero in the table and never used).  Both swaps of a row use the same table.
+// The loads are unconditional (every degree's slot has the same size), so a fetch issued for
+// the next row stays in flight while the current row is transformed.
 struct RowFrag {
     double a[2][2][4];
 };
 __device__ __forceinline__ void load_row_frag(const double *__restrict__ frag, int n, int lane, RowFrag &f)
 {
-    const int ks_n = big_ks(n);
-    const double *F = frag + big_swap_off(n);
+    const double *F = frag + big_swap_off(n < kBigOrder ? n : kBigOrder - 1) + lane;
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                f.a[pm][q][ks] = ks < ks_n ? F[((pm * 2 + q) * ks_n + ks) * 64 + lane] : 0.0;
+            for (int ks = 0; ks < 4; ++ks) f.a[pm][q][ks] = F[((pm * 2 + q) * 4 + ks) * 64];
 }
 
 // Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.  All of the
-// row's B values are read from LDS before the first product.
+// row's B values are read from LDS before the first product; orders past the degree read a
+// valid address and are replaced by zero.
 __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, int n, int lane, d4 (&D)[2][2])
 {
     const int ks_n = big_ks(n);
     const int t = lane & 15, kg = lane >> 4;
+    const double *Xn = X + n * (n + 1) * kBT + t;
     double b[2][2][4];
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
@@ -117,8 +119,11 @@ __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, int 
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
+                if (ks >= ks_n) break;
                 const int lc = 2 * (4 * ks + kg) + ((n + pm + q) & 1);
-                b[pm][q][ks] = (ks < ks_n && lc <= n) ? X[(n * (n + 1) + 2 * lc + q) * kBT + t] : 0.0;
+                const bool ok = lc <= n;
+                const double v = Xn[(2 * (ok ? lc : 0) + q) * kBT];
+                b[pm][q][ks] = ok ? v : 0.0;
             }
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
@@ -132,6 +137,48 @@ __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, int 
 #pragma unroll
             for (int q = 0; q < 2; ++q) D[pm][q] = mfma64(f.a[pm][q][ks], b[pm][q][ks], D[pm][q]);
     }
+}
+
+// Second swap of a row straight from the first swap's output registers: in the D layout,
+// element j of lane group g holds order m = 2 (4 j + g) + p of parity block p, which is exactly
+// the B operand of K step j, K index g, for the input-parity p = (n + pm + q) & 1 blocks.
+__device__ __forceinline__ void swap_row_regs(const RowFrag &f, int n, const d4 (&Din)[2][2], d4 (&D)[2][2])
+{
+    const int ks_n = big_ks(n);
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) D[pm][q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        if (ks >= ks_n) break;
+#pragma unroll
+        for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int pl = (n + pm + q) & 1;
+                D[pm][q] = mfma64(f.a[pm][q][ks], pl ? Din[1][q][ks] : Din[0][q][ks], D[pm][q]);
+            }
+    }
+}
+
+// Rotates the D blocks of row n in place by e^{+-i m angle} (powers k, k + 1 of the table).
+// Orders m > n are zero in D and their table entries may be unset, so they are left alone.
+__device__ __forceinline__ void rotate_regs(const BigLds &L, int n, int lane, d4 (&D)[2][2], int rot_k, double sgn)
+{
+    const int t = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = 2 * (4 * j + g) + pm;
+            if (m > n) continue;
+            const double c = L.pw[(rot_k * kBigOrder + m) * kBT + t];
+            const double s = sgn * L.pw[((rot_k + 1) * kBigOrder + m) * kBT + t];
+            const double re = D[pm][0][j], im = D[pm][1][j];
+            D[pm][0][j] = re * c - im * s;
+            D[pm][1][j] = re * s + im * c;
+        }
 }
 
 // Writes the D blocks of row n back to X, after an optional rotation by e^{+-i m angle}
@@ -248,46 +295,40 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // fragments are fetched while the current row is transformed ----
     {
         auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
-        RowFrag cur, nxt;
-        if (row_of(0) < p_in) load_row_frag(Ffw, row_of(0), lane, cur);
-        for (int n0 = 0; n0 < p_in; n0 += kWaves) {
-            const int n = row_of(n0);
-            if (n >= p_in) break;
-            const int nn = row_of(n0 + kWaves);
-            if (nn < p_in) load_row_frag(Ffw, nn, lane, nxt);
-            d4 D[2][2];
-            swap_row(cur, X, n, lane, D);
-            write_row(X, L, n, lane, D, 2, 1.0, nullptr);  // rotate by beta
-            swap_row(cur, X, n, lane, D);
-            write_row(X, L, n, lane, D, -1, 1.0, nullptr);
-            cur = nxt;
+        auto row = [&](const RowFrag &f, int n) {
+            d4 D[2][2], E[2][2];
+            swap_row(f, X, n, lane, D);
+            rotate_regs(L, n, lane, D, 2, 1.0);  // rotate by beta
+            swap_row_regs(f, n, D, E);
+            write_row(X, L, n, lane, E, -1, 1.0, nullptr);
+        };
+        RowFrag fa, fb;
+        load_row_frag(Ffw, row_of(0), lane, fa);
+        for (int n0 = 0; n0 < p_in; n0 += 2 * kWaves) {
+            if (row_of(n0) >= p_in) break;
+            load_row_frag(Ffw, row_of(n0 + kWaves), lane, fb);
+            row(fa, row_of(n0));
+            if (row_of(n0 + kWaves) >= p_in) break;
+            load_row_frag(Ffw, row_of(n0 + 2 * kWaves), lane, fa);
+            row(fb, row_of(n0 + kWaves));
         }
     }
     __syncthreads();
 
     // ---- z-translation, columns in snake order; the next column's fragments are fetched
-    // while the current column is multiplied ----
+    // (unconditionally, from fixed-size slots) while the current column is multiplied ----
     {
         const double *Zt = tab.bz[basis][OP];
         const int t = lane & 15, kg = lane >> 4;
         auto col_of = [&](int m0) { return m0 + (((m0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         auto load_z = [&](int m, double (&za)[2][8]) {
-            const double *Z = Zt + big_z_off(m);
-            const int kz = big_kz(m), mto = (p_out - m + 15) / 16;
-            const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
+            const double *Z = Zt + big_z_off(m < kBigOrder ? m : kBigOrder - 1) + lane;
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks)
-                    za[mt][ks] = (mt < mto && ks < ki) ? Z[(mt * kz + ks) * 64 + lane] : 0.0;
+                for (int ks = 0; ks < 8; ++ks) za[mt][ks] = Z[(mt * 8 + ks) * 64];
         };
-        double zcur[2][8], znxt[2][8];
-        if (col_of(0) < p_out) load_z(col_of(0), zcur);
-        for (int m0 = 0; m0 < p_out; m0 += kWaves) {
-            const int m = col_of(m0);
-            if (m >= p_out) break;
-            const int mn = col_of(m0 + kWaves);
-            if (mn < p_out) load_z(mn, znxt);
+        auto column = [&](const double (&za)[2][8], int m) {
             const int mto = (p_out - m + 15) / 16;
             const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
             double b[2][8];
@@ -295,8 +336,11 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int ks = 0; ks < 8; ++ks) {
+                    if (ks >= ki) break;
                     const int i = m + 4 * ks + kg;
-                    b[q][ks] = (ks < ki && i < p_in) ? X[(pos(i, m) + q) * kBT + t] : 0.0;
+                    const bool ok = i < p_in;
+                    const double v = X[(pos(ok ? i : m, m) + q) * kBT + t];
+                    b[q][ks] = ok ? v : 0.0;
                 }
             d4 res[2][2];
 #pragma unroll
@@ -306,8 +350,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 #pragma unroll
                     for (int ks = 0; ks < 8; ++ks) {
                         if (ks >= ki) break;
-                        a0 = mfma64(zcur[mt][ks], b[0][ks], a0);
-                        a1 = mfma64(zcur[mt][ks], b[1][ks], a1);
+                        a0 = mfma64(za[mt][ks], b[0][ks], a0);
+                        a1 = mfma64(za[mt][ks], b[1][ks], a1);
                     }
                 }
                 res[0][mt] = a0;
@@ -324,10 +368,16 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
                     X[(pos(o, m) + 1) * kBT + t] = m ? res[1][mt][j] : 0.0;
                 }
             }
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) zcur[mt][ks] = znxt[mt][ks];
+        };
+        double za[2][8], zb[2][8];
+        load_z(col_of(0), za);
+        for (int m0 = 0; m0 < p_out; m0 += 2 * kWaves) {
+            if (col_of(m0) >= p_out) break;
+            load_z(col_of(m0 + kWaves), zb);
+            column(za, col_of(m0));
+            if (col_of(m0 + kWaves) >= p_out) break;
+            load_z(col_of(m0 + 2 * kWaves), za);
+            column(zb, col_of(m0 + kWaves));
         }
     }
     __syncthreads();
@@ -335,19 +385,22 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // ---- backward rotation, unscale ----
     {
         auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
-        RowFrag cur, nxt;
-        if (row_of(0) < p_out) load_row_frag(Fbw, row_of(0), lane, cur);
-        for (int n0 = 0; n0 < p_out; n0 += kWaves) {
-            const int n = row_of(n0);
-            if (n >= p_out) break;
-            const int nn = row_of(n0 + kWaves);
-            if (nn < p_out) load_row_frag(Fbw, nn, lane, nxt);
-            d4 D[2][2];
-            swap_row(cur, X, n, lane, D);
-            write_row(X, L, n, lane, D, 2, -1.0, nullptr);   // rotate by -beta
-            swap_row(cur, X, n, lane, D);
-            write_row(X, L, n, lane, D, 0, -1.0, L.scout);   // rotate by -alpha, unscale
-            cur = nxt;
+        auto row = [&](const RowFrag &f, int n) {
+            d4 D[2][2], E[2][2];
+            swap_row(f, X, n, lane, D);
+            rotate_regs(L, n, lane, D, 2, -1.0);  // rotate by -beta
+            swap_row_regs(f, n, D, E);
+            write_row(X, L, n, lane, E, 0, -1.0, L.scout);  // rotate by -alpha, unscale
+        };
+        RowFrag fa, fb;
+        load_row_frag(Fbw, row_of(0), lane, fa);
+        for (int n0 = 0; n0 < p_out; n0 += 2 * kWaves) {
+            if (row_of(n0) >= p_out) break;
+            load_row_frag(Fbw, row_of(n0 + kWaves), lane, fb);
+            row(fa, row_of(n0));
+            if (row_of(n0 + kWaves) >= p_out) break;
+            load_row_frag(Fbw, row_of(n0 + 2 * kWaves), lane, fa);
+            row(fb, row_of(n0 + kWaves));
         }
     }
     __syncthreads();

@@ -49,27 +49,20 @@ __host__ __device__ constexpr int packed_off(int n)
 
 // MFMA fragment tables of the block kernel for orders up to kBigOrder (FP64 16x16x4 A operands,
 // 64 doubles per fragment, lane l holding row l % 16 and K index l / 16 of the 16 x 4 block).
-//  * swap: for degree n, output-order parity pm, part q (0: real-part matrix, 1: imaginary),
-//    K step ks < big_ks(n): entry (m = 2 (l % 16) + pm, l' = 2 (4 ks + l / 16) + ((n + pm + q) & 1))
-//    of the (n+1) x (n+1) swap matrix (zero outside the degree and, for q = 1, in row or
-//    column 0): the chequerboard splits every swap into two dense blocks by parity.
-//  * z: for column m, output tile mt < big_mt(m), K step ks < big_kz(m): entry
-//    (out = m + 16 mt + l % 16, in = m + 4 ks + l / 16) of the column's z matrix.
+// Every degree and every column has a slot of the same size, zero-padded past the K steps and
+// tiles it uses, so a wavefront can fetch any slot with unconditional loads.
+//  * swap: degree n's slot holds, for output-order parity pm, part q (0: real-part matrix,
+//    1: imaginary) and K step ks < 4, fragment (pm * 2 + q) * 4 + ks with entry
+//    (m = 2 (l % 16) + pm, l' = 2 (4 ks + l / 16) + ((n + pm + q) & 1)) of the (n+1) x (n+1)
+//    swap matrix (zero outside the degree and, for q = 1, in row or column 0): the
+//    chequerboard splits every swap into two dense blocks by parity.  Only the first
+//    big_ks(n) K steps can be nonzero.
+//  * z: column m's slot holds, for output tile mt < 2 and K step ks < 8, fragment mt * 8 + ks
+//    with entry (out = m + 16 mt + l % 16, in = m + 4 ks + l / 16) of the column's z matrix.
 constexpr int kBigOrder = 32;
+constexpr int kBigSlot = 16 * 64;  // doubles per degree or column slot
 __host__ __device__ constexpr int big_ks(int n) { return (n / 2 + 4) / 4; }
-__host__ __device__ constexpr int big_swap_off(int n)
-{
-    int c = 0;
-    for (int j = 0; j < n; ++j) c += 4 * big_ks(j) * 64;
-    return c;
-}
-__host__ __device__ constexpr int big_mt(int m) { return (kBigOrder - m + 15) / 16; }
-__host__ __device__ constexpr int big_kz(int m) { return (kBigOrder - m + 3) / 4; }
-__host__ __device__ constexpr int big_z_off(int m)
-{
-    int c = 0;
-    for (int j = 0; j < m; ++j) c += big_mt(j) * big_kz(j) * 64;
-    return c;
-}
+__host__ __device__ constexpr int big_swap_off(int n) { return n * kBigSlot; }
+__host__ __device__ constexpr int big_z_off(int m) { return m * kBigSlot; }
 
 }  // namespace shfmm

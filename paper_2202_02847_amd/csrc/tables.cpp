@@ -224,13 +224,13 @@ void build_tables(int P, HostTables &t)
                     for (int q = 0; q < 2; ++q) {
                         const auto &dense = basis ? t.swap64n[2 * side + q] : t.swap64[2 * side + q];
                         const int pl = (n + pm + q) & 1;
-                        for (int ks = 0; ks < big_ks(n); ++ks)
+                        for (int ks = 0; ks < 4; ++ks)
                             for (int l = 0; l < 64; ++l) {
                                 const int m = 2 * (l % 16) + pm, lc = 2 * (4 * ks + l / 16) + pl;
                                 double v = 0.0;
-                                if (m <= n && lc <= n && !(q == 1 && (m == 0 || lc == 0)))
+                                if (ks < big_ks(n) && m <= n && lc <= n && !(q == 1 && (m == 0 || lc == 0)))
                                     v = dense[off + m * (n + 1) + lc];
-                                out[big_swap_off(n) + ((pm * 2 + q) * big_ks(n) + ks) * 64 + l] = v;
+                                out[big_swap_off(n) + ((pm * 2 + q) * 4 + ks) * 64 + l] = v;
                             }
                     }
             }
@@ -255,14 +255,14 @@ void build_tables(int P, HostTables &t)
             auto &out = t.bz[basis][k];
             out.assign(big_z_off(kBigOrder), 0.0);
             for (int m = 0; m < kBigOrder && m < P; ++m)
-                for (int mt = 0; mt < big_mt(m); ++mt)
-                    for (int ks = 0; ks < big_kz(m); ++ks)
+                for (int mt = 0; mt < 2; ++mt)
+                    for (int ks = 0; ks < 8; ++ks)
                         for (int l = 0; l < 64; ++l) {
                             const int o = m + 16 * mt + l % 16, i = m + 4 * ks + l / 16;
                             double v = 0.0;
                             if (o < kBigOrder && i < kBigOrder && o < P && i < P)
                                 v = (double)z_coefficient((ZKind)k, m, o, i, basis == 1);
-                            out[big_z_off(m) + (mt * big_kz(m) + ks) * 64 + l] = v;
+                            out[big_z_off(m) + (mt * 8 + ks) * 64 + l] = v;
                         }
         }
     }
