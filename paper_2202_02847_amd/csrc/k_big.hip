@@ -31,6 +31,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kBT = 16;     // translations per block
 constexpr int kWaves = 8;   // wavefronts per workgroup (two per SIMD, to hide each other's latency)
 constexpr int kThreads = 64 * kWaves;
+static_assert(kThreads == kBT * kBigOrder, "the power tables take one thread per (order, translation)");
 
 template <typename Real>
 struct Pair2;
@@ -211,6 +212,33 @@ __device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int
         }
 }
 
+// Final form of row n straight to memory: rotation by e^{-i m alpha} (powers 0, 1 of the
+// table), the output scale, and the store of every order m <= n of translations t < nt.
+template <typename Real>
+__device__ __forceinline__ void store_row(Real *__restrict__ aout, const BigLds &L, int n, int lane, const d4 (&D)[2][2],
+                                          int nt)
+{
+    using R2 = typename Pair2<Real>::T;
+    const int t = lane & 15, g = lane >> 4;
+    if (t >= nt) return;
+    R2 *row = reinterpret_cast<R2 *>(aout + L.ooff[t]) + n * (n + 1) / 2;
+    const double f = L.scout[n * kBT + t];
+#pragma unroll
+    for (int pm = 0; pm < 2; ++pm)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = 2 * (4 * j + g) + pm;
+            if (m > n) continue;
+            const double c = L.pw[(0 * kBigOrder + m) * kBT + t];
+            const double sn = -L.pw[(1 * kBigOrder + m) * kBT + t];
+            const double re = D[pm][0][j], im = D[pm][1][j];
+            R2 w;
+            w.x = (Real)((re * c - im * sn) * f);
+            w.y = m ? (Real)((re * sn + im * c) * f) : (Real)0;
+            row[m] = w;
+        }
+}
+
 // One block of up to 16 translations whose offsets and shifts are in L (t >= nt repeat the
 // last valid translation and are not stored).
 template <typename Real, int OP>
@@ -224,34 +252,49 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     const int PM = p_in > p_out ? p_in : p_out;
     double *X = L.X;
 
-    // ---- geometry, powers and scales, one thread per translation ----
-    if (tid < kBT) {
-        const int t = tid;
+    // ---- geometry, powers and scales: thread (m, t) fills order m of translation t, every
+    // order below kBigOrder (powers by repeated squaring) ----
+    {
+        const int t = tid & 15, m = tid >> 4;
         const Geometry g = shift_geometry(L.r[3 * t], L.r[3 * t + 1], L.r[3 * t + 2]);
         const bool ok = g.valid == 1;
-        L.bad[t] = ok ? 0 : (g.valid == 0 ? 1 : 2);
-        const double ca = ok ? g.ca : 1.0, sa = ok ? g.sa : 0.0, cb = ok ? g.cb : 1.0, sb = ok ? g.sb : 0.0;
-        const double R = ok ? g.R : 1.0, s = ok ? g.s : 1.0;
-        double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0, rn = 1.0, sn = 1.0;
-        for (int m = 0; m < PM; ++m) {
-            L.pw[(0 * kBigOrder + m) * kBT + t] = c1;
-            L.pw[(1 * kBigOrder + m) * kBT + t] = s1;
-            L.pw[(2 * kBigOrder + m) * kBT + t] = c2;
-            L.pw[(3 * kBigOrder + m) * kBT + t] = s2;
-            const double t1 = c1 * ca - s1 * sa;
-            s1 = c1 * sa + s1 * ca;
-            c1 = t1;
-            const double t2 = c2 * cb - s2 * sb;
-            s2 = c2 * sb + s2 * cb;
-            c2 = t2;
-            // rn = R^m, sn = s^m
-            L.scin[m * kBT + t] = (OP == OP_L2L) ? rn : sn * s;
-            L.scout[m * kBT + t] = (OP == OP_M2M) ? rn * R : sn;
-            rn *= R;
-            sn *= s;
+        if (m == 0) L.bad[t] = ok ? 0 : (g.valid == 0 ? 1 : 2);
+        double ca = ok ? g.ca : 1.0, sa = ok ? g.sa : 0.0, cb = ok ? g.cb : 1.0, sb = ok ? g.sb : 0.0;
+        double R = ok ? g.R : 1.0, sr = ok ? g.s : 1.0;
+        const double R1 = R, s1 = sr;
+        double c1 = 1.0, s1m = 0.0, c2 = 1.0, s2m = 0.0, rn = 1.0, sn = 1.0;
+        for (int k = m; k; k >>= 1) {
+            if (k & 1) {
+                const double u1 = c1 * ca - s1m * sa;
+                s1m = c1 * sa + s1m * ca;
+                c1 = u1;
+                const double u2 = c2 * cb - s2m * sb;
+                s2m = c2 * sb + s2m * cb;
+                c2 = u2;
+                rn *= R;
+                sn *= sr;
+            }
+            const double v1 = ca * ca - sa * sa;
+            sa = 2.0 * ca * sa;
+            ca = v1;
+            const double v2 = cb * cb - sb * sb;
+            sb = 2.0 * cb * sb;
+            cb = v2;
+            R *= R;
+            sr *= sr;
         }
+        L.pw[(0 * kBigOrder + m) * kBT + t] = c1;
+        L.pw[(1 * kBigOrder + m) * kBT + t] = s1m;
+        L.pw[(2 * kBigOrder + m) * kBT + t] = c2;
+        L.pw[(3 * kBigOrder + m) * kBT + t] = s2m;
+        // rn = R^m, sn = s^m
+        L.scin[m * kBT + t] = (OP == OP_L2L) ? rn : sn * s1;
+        L.scout[m * kBT + t] = (OP == OP_M2M) ? rn * R1 : sn;
     }
     __syncthreads();
+    // outputs go straight from the backward rotation to memory unless the call accumulates
+    // or a translation of the block has a zero or non-finite shift
+    const bool fused = !acc_out && __ballot(lane < kBT && L.bad[lane & 15] != 0) == 0;
 
     // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Each thread issues up to
     // 16 loads before it uses any, so most of a block's loads are in flight together ----
@@ -390,7 +433,10 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
             swap_row(f, X, n, lane, D);
             rotate_regs(L, n, lane, D, 2, -1.0);  // rotate by -beta
             swap_row_regs(f, n, D, E);
-            write_row(X, L, n, lane, E, 0, -1.0, L.scout);  // rotate by -alpha, unscale
+            if (fused)
+                store_row<Real>(aout, L, n, lane, E, nt);   // rotate by -alpha, unscale, store
+            else
+                write_row(X, L, n, lane, E, 0, -1.0, L.scout);  // rotate by -alpha, unscale
         };
         RowFrag fa, fb;
         load_row_frag(Fbw, row_of(0), lane, fa);
@@ -405,8 +451,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     }
     __syncthreads();
 
-    // ---- store ----
-    {
+    // ---- store (when the backward rotation did not store already) ----
+    if (!fused) {
         const int npair = p_out * (p_out + 1) / 2;
         for (int idx = tid; idx < npair * kBT; idx += kThreads) {
             const int t = idx & 15, p = idx >> 4;
