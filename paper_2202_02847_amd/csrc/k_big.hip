@@ -44,30 +44,51 @@ struct Pair2<float> {
     using T = float2;
 };
 
-// LDS carve-up (in doubles): X[S][16] | powers[4][32][16] | scale_in[32][16] | scale_out[32][16]
-// | in offsets[16] | out offsets[16] | shifts[16][3] | bad flags[16]
+// LDS carve-up (in doubles): (n, m) of pair p[528] | X[S][16] | powers[4][32][16] | scale_in[32][16]
+// | scale_out[32][16] | in offsets[16] | out offsets[16] | shifts[16][3] | bad flags[16].  The pair
+// table comes first so that its place does not depend on the orders of a task.
+constexpr int kBigPairs = kBigOrder * (kBigOrder + 1) / 2;
+static_assert(kBigPairs % 4 == 0, "the pair table fills whole doubles");
 struct BigLds {
     double *X, *pw, *scin, *scout, *r;
     int64_t *ioff, *ooff;
     int *bad;
+    unsigned short *nm;  // 32 n + m of pair index p = n (n + 1) / 2 + m
 };
 
-__host__ __device__ constexpr size_t big_lds_doubles(int PM)
+// Offsets (in doubles) of the LDS carve-up; big_lds and the launch size both come from here.
+struct BigLdsOffsets {
+    size_t X, pw, scin, scout, ioff, ooff, r, bad, end;
+};
+__host__ __device__ constexpr BigLdsOffsets big_lds_offsets(int PM)
 {
-    return (size_t)PM * (PM + 1) * kBT + 4 * kBigOrder * kBT + 2 * kBigOrder * kBT + 2 * kBT + 3 * kBT + kBT / 2;
+    BigLdsOffsets o{};
+    o.X = kBigPairs / 4;
+    o.pw = o.X + (size_t)PM * (PM + 1) * kBT;
+    o.scin = o.pw + 4 * kBigOrder * kBT;
+    o.scout = o.scin + kBigOrder * kBT;
+    o.ioff = o.scout + kBigOrder * kBT;
+    o.ooff = o.ioff + kBT;
+    o.r = o.ooff + kBT;
+    o.bad = o.r + 3 * kBT;
+    o.end = o.bad + kBT / 2;
+    return o;
 }
+__host__ __device__ constexpr size_t big_lds_doubles(int PM) { return big_lds_offsets(PM).end; }
 
 __device__ __forceinline__ BigLds big_lds(double *sm, int PM)
 {
+    const BigLdsOffsets o = big_lds_offsets(PM);
     BigLds L;
-    L.X = sm;
-    L.pw = sm + (size_t)PM * (PM + 1) * kBT;
-    L.scin = L.pw + 4 * kBigOrder * kBT;
-    L.scout = L.scin + kBigOrder * kBT;
-    L.ioff = reinterpret_cast<int64_t *>(L.scout + kBigOrder * kBT);
-    L.ooff = L.ioff + kBT;
-    L.r = reinterpret_cast<double *>(L.ooff + kBT);
-    L.bad = reinterpret_cast<int *>(L.r + 3 * kBT);
+    L.nm = reinterpret_cast<unsigned short *>(sm);
+    L.X = sm + o.X;
+    L.pw = sm + o.pw;
+    L.scin = sm + o.scin;
+    L.scout = sm + o.scout;
+    L.ioff = reinterpret_cast<int64_t *>(sm + o.ioff);
+    L.ooff = reinterpret_cast<int64_t *>(sm + o.ooff);
+    L.r = sm + o.r;
+    L.bad = reinterpret_cast<int *>(sm + o.bad);
     return L;
 }
 
@@ -80,6 +101,16 @@ __device__ __forceinline__ int pair_degree(int p)
     while ((n + 1) * (n + 2) / 2 <= p) ++n;
     while (n * (n + 1) / 2 > p) --n;
     return n;
+}
+
+// Fills the (n, m) table of every pair index below kBigPairs; it depends on nothing else, so a
+// workgroup fills it once, before its first barrier.
+__device__ __forceinline__ void fill_pair_table(const BigLds &L)
+{
+    for (int p = threadIdx.x; p < kBigPairs; p += blockDim.x) {
+        const int n = pair_degree(p);
+        L.nm[p] = (unsigned short)(32 * n + (p - n * (n + 1) / 2));
+    }
 }
 
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
@@ -296,33 +327,33 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // or a translation of the block has a zero or non-finite shift
     const bool fused = !acc_out && __ballot(lane < kBT && L.bad[lane & 15] != 0) == 0;
 
-    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Each thread issues up to
-    // 16 loads before it uses any, so most of a block's loads are in flight together ----
+    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Thread (s, t) takes pairs
+    // p = s + 32 u of translation t, so its source row, and the immediate offsets of its loads
+    // and LDS stores, are fixed; each thread has all of its loads in flight before it uses one ----
     {
         constexpr int U = 16;
-        const int total = PM * (PM + 1) / 2 * kBT;
-        for (int base = 0; base < total; base += kThreads * U) {
+        const int t = tid & 15, s0 = tid >> 4;
+        const int npair = PM * (PM + 1) / 2, npin = p_in * (p_in + 1) / 2;
+        const R2 *src = reinterpret_cast<const R2 *>(ain + L.ioff[t]);
+        for (int base = 0; base < npair; base += 32 * U) {
             R2 v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + kThreads * u;
-                const int t = idx & 15, p = idx >> 4;
-                const int n = idx < total ? pair_degree(p) : PM;
-                v[u] = (n < p_in) ? *reinterpret_cast<const R2 *>(ain + L.ioff[t] + 2 * p) : R2{};
+                const int p = base + s0 + 32 * u;
+                v[u] = p < npin ? src[p] : R2{};
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + kThreads * u;
-                if (idx >= total) continue;
-                const int t = idx & 15, p = idx >> 4;
-                const int n = pair_degree(p), m = p - n * (n + 1) / 2;
+                const int p = base + s0 + 32 * u;
+                if (p >= npair) break;
+                const int nm = L.nm[p], n = nm >> 5, m = nm & 31;
                 double re = 0.0, im = 0.0;
-                if (n < p_in) {
+                if (p < npin) {
                     const double f = L.scin[n * kBT + t];
                     const double a = (double)v[u].x * f, b = m ? (double)v[u].y * f : 0.0;
-                    const double c = L.pw[(0 * kBigOrder + m) * kBT + t], s = L.pw[(1 * kBigOrder + m) * kBT + t];
-                    re = a * c - b * s;
-                    im = m ? a * s + b * c : 0.0;
+                    const double c = L.pw[(0 * kBigOrder + m) * kBT + t], sn = L.pw[(1 * kBigOrder + m) * kBT + t];
+                    re = a * c - b * sn;
+                    im = m ? a * sn + b * c : 0.0;
                 }
                 X[(2 * p) * kBT + t] = re;
                 X[(2 * p + 1) * kBT + t] = im;
@@ -496,6 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_big(DevTables tab, TransArgs a)
     const Real *ain = reinterpret_cast<const Real *>(a.in);
     Real *aout = reinterpret_cast<Real *>(a.out);
     const Real *rr = reinterpret_cast<const Real *>(a.r);
+    fill_pair_table(L);
     const int64_t nblk = (a.count + kBT - 1) / kBT;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const int64_t first = blk * kBT;
@@ -547,6 +579,7 @@ __global__ __launch_bounds__(kThreads) void k_big_list(DevTables tab, ListArgs l
     extern __shared__ double sm[];
     const Real *ain = reinterpret_cast<const Real *>(la.arena_in);
     Real *aout = reinterpret_cast<Real *>(la.arena_out);
+    fill_pair_table(big_lds(sm, 2));
     for (int64_t task = blockIdx.x; task < la.ntasks; task += gridDim.x) {
         const ListTask tk = la.tasks[task];
         const int p_in = tk.p_in, p_out = tk.p_out, nt = tk.count;
