@@ -92,8 +92,6 @@ __device__ __forceinline__ BigLds big_lds(double *sm, int PM)
     return L;
 }
 
-__device__ __forceinline__ int pos(int n, int m) { return n * (n + 1) + 2 * m; }
-
 // degree n of pair index p (p = n(n+1)/2 + m)
 __device__ __forceinline__ int pair_degree(int p)
 {
@@ -118,6 +116,17 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Index (in doubles) of element (pair p, translation t) in X: the real part, followed by the
+// imaginary part, so one 16-byte LDS access moves both.
+__device__ __forceinline__ int xe(int p, int t) { return (p * kBT + t) * 2; }
+// Index of (cos, sin) of m times angle k (0: alpha, 1: beta) of translation t in the power table.
+__device__ __forceinline__ int pwi(int k, int m, int t) { return ((k * kBigOrder + m) * kBT + t) * 2; }
+__device__ __forceinline__ double2 lds2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+__device__ __forceinline__ void sts2(double *p, double a, double b) { *reinterpret_cast<double2 *>(p) = double2{a, b}; }
+// Waits until every vector memory operation this wavefront has issued is complete (the
+// compiler does not track LDS written by direct loads).
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Operator fragments of row n (both parities and parts, every K step; K steps past the
 // row's count are zero in the table and never used).  Both swaps of a row use the same table.
 // The loads are unconditional (every degree's slot has the same size), so a fetch issued for
@@ -136,27 +145,43 @@ __device__ __forceinline__ void load_row_frag(const double *__restrict__ frag, i
             for (int ks = 0; ks < 4; ++ks) f.a[pm][q][ks] = F[((pm * 2 + q) * 4 + ks) * 64];
 }
 
-// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.  All of the
-// row's B values are read from LDS before the first product; orders past the degree read a
-// valid address and are replaced by zero.
-__device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, int n, int lane, d4 (&D)[2][2])
+// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.  Each lane
+// reads (re, im) of the two input orders of its K index and step (one per parity) before the
+// first product; orders past the degree read a valid address and are replaced by zero.  With
+// RAW the row holds the input as loaded: Im C_n^0 is dropped, and the scale and the rotation by
+// e^{i m alpha} are applied here.
+template <bool RAW>
+__device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, const BigLds &L, int n, int lane,
+                                         d4 (&D)[2][2])
 {
     const int ks_n = big_ks(n);
     const int t = lane & 15, kg = lane >> 4;
-    const double *Xn = X + n * (n + 1) * kBT + t;
+    const double *Xn = X + xe(n * (n + 1) / 2, t);
+    const double sc = RAW ? L.scin[n * kBT + t] : 1.0;
     double b[2][2][4];
 #pragma unroll
-    for (int pm = 0; pm < 2; ++pm)
+    for (int ks = 0; ks < 4; ++ks) {
+        if (ks >= ks_n) break;
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                if (ks >= ks_n) break;
-                const int lc = 2 * (4 * ks + kg) + ((n + pm + q) & 1);
-                const bool ok = lc <= n;
-                const double v = Xn[(2 * (ok ? lc : 0) + q) * kBT];
-                b[pm][q][ks] = ok ? v : 0.0;
+        for (int par = 0; par < 2; ++par) {
+            const int lc = 2 * (4 * ks + kg) + par;
+            const bool ok = lc <= n;
+            const int l = ok ? lc : 0;
+            const double2 v = lds2(Xn + l * 2 * kBT);
+            double re = v.x, im = v.y;
+            if (RAW) {
+                const double2 cs = lds2(L.pw + pwi(0, l, t));
+                const double a = re * sc, c = l ? im * sc : 0.0;
+                re = a * cs.x - c * cs.y;
+                im = l ? a * cs.y + c * cs.x : 0.0;
             }
+            // input parity par feeds (pm, q) with (n + pm + q) & 1 == par
+            const int pm0 = (par + n) & 1, pm1 = (par + n + 1) & 1;
+            const double r0 = ok ? re : 0.0, i0 = ok ? im : 0.0;
+            if (pm0) b[1][0][ks] = r0; else b[0][0][ks] = r0;
+            if (pm1) b[1][1][ks] = i0; else b[0][1][ks] = i0;
+        }
+    }
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
@@ -194,9 +219,8 @@ __device__ __forceinline__ void swap_row_regs(const RowFrag &f, int n, const d4 
     }
 }
 
-// Rotates the D blocks of row n in place by e^{+-i m angle} (powers k, k + 1 of the table).
-// Orders m > n are zero in D and their table entries may be unset, so they are left alone.
-__device__ __forceinline__ void rotate_regs(const BigLds &L, int n, int lane, d4 (&D)[2][2], int rot_k, double sgn)
+// Rotates the D blocks of row n in place by e^{+-i m beta}.  Orders m > n are zero in D.
+__device__ __forceinline__ void rotate_beta(const BigLds &L, int n, int lane, d4 (&D)[2][2], double sgn)
 {
     const int t = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -205,20 +229,21 @@ __device__ __forceinline__ void rotate_regs(const BigLds &L, int n, int lane, d4
         for (int j = 0; j < 4; ++j) {
             const int m = 2 * (4 * j + g) + pm;
             if (m > n) continue;
-            const double c = L.pw[(rot_k * kBigOrder + m) * kBT + t];
-            const double s = sgn * L.pw[((rot_k + 1) * kBigOrder + m) * kBT + t];
+            const double2 cs = lds2(L.pw + pwi(1, m, t));
+            const double s = sgn * cs.y;
             const double re = D[pm][0][j], im = D[pm][1][j];
-            D[pm][0][j] = re * c - im * s;
-            D[pm][1][j] = re * s + im * c;
+            D[pm][0][j] = re * cs.x - im * s;
+            D[pm][1][j] = re * s + im * cs.x;
         }
 }
 
-// Writes the D blocks of row n back to X, after an optional rotation by e^{+-i m angle}
-// (powers k, k + 1 of the table) and an optional scale per translation.
-__device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int lane, const d4 (&D)[2][2], int rot_k,
-                                          double sgn, const double *scale)
+// Writes the D blocks of row n back to X, after an optional rotation by e^{-i m alpha} and
+// scale per translation.
+__device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int lane, const d4 (&D)[2][2], bool unrotate)
 {
     const int t = lane & 15, g = lane >> 4;
+    double *Xn = X + xe(n * (n + 1) / 2, t);
+    const double f = unrotate ? L.scout[n * kBT + t] : 1.0;
 #pragma unroll
     for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
@@ -226,25 +251,18 @@ __device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int
             const int m = 2 * (4 * j + g) + pm;
             if (m > n) continue;
             double re = D[pm][0][j], im = D[pm][1][j];
-            if (rot_k >= 0) {
-                const double c = L.pw[(rot_k * kBigOrder + m) * kBT + t];
-                const double s = sgn * L.pw[((rot_k + 1) * kBigOrder + m) * kBT + t];
+            if (unrotate) {
+                const double2 cs = lds2(L.pw + pwi(0, m, t));
                 const double a = re;
-                re = a * c - im * s;
-                im = a * s + im * c;
+                re = (a * cs.x + im * cs.y) * f;
+                im = (im * cs.x - a * cs.y) * f;
             }
-            if (scale) {
-                const double f = scale[n * kBT + t];
-                re *= f;
-                im *= f;
-            }
-            X[pos(n, m) * kBT + t] = re;
-            X[(pos(n, m) + 1) * kBT + t] = m ? im : 0.0;
+            sts2(Xn + m * 2 * kBT, re, m ? im : 0.0);
         }
 }
 
-// Final form of row n straight to memory: rotation by e^{-i m alpha} (powers 0, 1 of the
-// table), the output scale, and the store of every order m <= n of translations t < nt.
+// Final form of row n straight to memory: rotation by e^{-i m alpha}, the output scale, and
+// the store of every order m <= n of translations t < nt.
 template <typename Real>
 __device__ __forceinline__ void store_row(Real *__restrict__ aout, const BigLds &L, int n, int lane, const d4 (&D)[2][2],
                                           int nt)
@@ -260,14 +278,29 @@ __device__ __forceinline__ void store_row(Real *__restrict__ aout, const BigLds 
         for (int j = 0; j < 4; ++j) {
             const int m = 2 * (4 * j + g) + pm;
             if (m > n) continue;
-            const double c = L.pw[(0 * kBigOrder + m) * kBT + t];
-            const double sn = -L.pw[(1 * kBigOrder + m) * kBT + t];
+            const double2 cs = lds2(L.pw + pwi(0, m, t));
             const double re = D[pm][0][j], im = D[pm][1][j];
             R2 w;
-            w.x = (Real)((re * c - im * sn) * f);
-            w.y = m ? (Real)((re * sn + im * c) * f) : (Real)0;
+            w.x = (Real)((re * cs.x + im * cs.y) * f);
+            w.y = m ? (Real)((im * cs.x - re * cs.y) * f) : (Real)0;
             row[m] = w;
         }
+}
+
+// Issues the direct-to-LDS loads of input row n (pairs n(n+1)/2 .. n(n+1)/2 + n of every
+// translation) into its place in X: each instruction moves 4 pairs of the 16 translations,
+// lane l taking pair 4 i + l / 16 of translation l % 16, which is X's own order.
+__device__ __forceinline__ void dma_row(const double *__restrict__ ain, const BigLds &L, int n, int lane)
+{
+    const int t = lane & 15, pl = lane >> 4;
+    const int p0 = n * (n + 1) / 2;
+    const double *src = ain + L.ioff[t] + 2 * (p0 + pl);
+    for (int i = 0; 4 * i <= n; ++i) {
+        if (4 * i + pl <= n)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + 8 * i),
+                                             (__attribute__((address_space(3))) void *)(L.X + xe(p0 + 4 * i, 0)), 16,
+                                             0, 0);
+    }
 }
 
 // One block of up to 16 translations whose offsets and shifts are in L (t >= nt repeat the
@@ -278,10 +311,17 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 {
     using R2 = typename Pair2<Real>::T;
     constexpr int basis = sizeof(Real) == 4 ? 1 : 0;
+    // FP64 inputs go from memory to LDS as they are, one row ahead of the forward rotation
+    // that uses them; FP32 inputs pass through registers (to widen them) in a load phase.
+    constexpr bool direct = sizeof(Real) == 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int PM = p_in > p_out ? p_in : p_out;
     double *X = L.X;
+    auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
+
+    if constexpr (direct) {
+        if (row_of(0) < p_in) dma_row(reinterpret_cast<const double *>(ain), L, row_of(0), lane);
+    }
 
     // ---- geometry, powers and scales: thread (m, t) fills order m of translation t, every
     // order below kBigOrder (powers by repeated squaring) ----
@@ -314,10 +354,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
             R *= R;
             sr *= sr;
         }
-        L.pw[(0 * kBigOrder + m) * kBT + t] = c1;
-        L.pw[(1 * kBigOrder + m) * kBT + t] = s1m;
-        L.pw[(2 * kBigOrder + m) * kBT + t] = c2;
-        L.pw[(3 * kBigOrder + m) * kBT + t] = s2m;
+        sts2(L.pw + pwi(0, m, t), c1, s1m);
+        sts2(L.pw + pwi(1, m, t), c2, s2m);
         // rn = R^m, sn = s^m
         L.scin[m * kBT + t] = (OP == OP_L2L) ? rn : sn * s1;
         L.scout[m * kBT + t] = (OP == OP_M2M) ? rn * R1 : sn;
@@ -327,15 +365,15 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // or a translation of the block has a zero or non-finite shift
     const bool fused = !acc_out && __ballot(lane < kBT && L.bad[lane & 15] != 0) == 0;
 
-    // ---- load: scale and rotate by alpha; rows >= p_in are zero.  Thread (s, t) takes pairs
-    // p = s + 32 u of translation t, so its source row, and the immediate offsets of its loads
-    // and LDS stores, are fixed; each thread has all of its loads in flight before it uses one ----
-    {
+    // ---- FP32 load: widen, scale and rotate by alpha.  Thread (s, t) takes pairs p = s + 32 u
+    // of translation t, so its source row and the immediate offsets of its loads and LDS stores
+    // are fixed; each thread has all of its loads in flight before it uses one ----
+    if constexpr (!direct) {
         constexpr int U = 16;
         const int t = tid & 15, s0 = tid >> 4;
-        const int npair = PM * (PM + 1) / 2, npin = p_in * (p_in + 1) / 2;
+        const int npin = p_in * (p_in + 1) / 2;
         const R2 *src = reinterpret_cast<const R2 *>(ain + L.ioff[t]);
-        for (int base = 0; base < npair; base += 32 * U) {
+        for (int base = 0; base < npin; base += 32 * U) {
             R2 v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -345,45 +383,45 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = base + s0 + 32 * u;
-                if (p >= npair) break;
+                if (p >= npin) break;
                 const int nm = L.nm[p], n = nm >> 5, m = nm & 31;
-                double re = 0.0, im = 0.0;
-                if (p < npin) {
-                    const double f = L.scin[n * kBT + t];
-                    const double a = (double)v[u].x * f, b = m ? (double)v[u].y * f : 0.0;
-                    const double c = L.pw[(0 * kBigOrder + m) * kBT + t], sn = L.pw[(1 * kBigOrder + m) * kBT + t];
-                    re = a * c - b * sn;
-                    im = m ? a * sn + b * c : 0.0;
-                }
-                X[(2 * p) * kBT + t] = re;
-                X[(2 * p + 1) * kBT + t] = im;
+                const double f = L.scin[n * kBT + t];
+                const double a = (double)v[u].x * f, b = m ? (double)v[u].y * f : 0.0;
+                const double2 cs = lds2(L.pw + pwi(0, m, t));
+                sts2(X + xe(p, t), a * cs.x - b * cs.y, m ? a * cs.y + b * cs.x : 0.0);
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     const int fw = (OP == OP_L2L) ? 1 : 0, bw = (OP == OP_M2M) ? 0 : 1;
     const double *Ffw = tab.bsw[basis][fw], *Fbw = tab.bsw[basis][bw];
 
     // ---- forward rotation, rows in snake order over the wavefronts; the next row's
-    // fragments are fetched while the current row is transformed ----
+    // fragments (and, for FP64, its input) are fetched while the current row is transformed ----
     {
-        auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         auto row = [&](const RowFrag &f, int n) {
             d4 D[2][2], E[2][2];
-            swap_row(f, X, n, lane, D);
-            rotate_regs(L, n, lane, D, 2, 1.0);  // rotate by beta
+            swap_row<direct>(f, X, L, n, lane, D);
+            rotate_beta(L, n, lane, D, 1.0);
             swap_row_regs(f, n, D, E);
-            write_row(X, L, n, lane, E, -1, 1.0, nullptr);
+            write_row(X, L, n, lane, E, false);
+        };
+        auto fetch = [&](int n, RowFrag &f) {
+            if constexpr (direct) {
+                wait_vm_all();  // the current row's input and fragments have landed
+                if (n < p_in) dma_row(reinterpret_cast<const double *>(ain), L, n, lane);
+            }
+            load_row_frag(Ffw, n, lane, f);
         };
         RowFrag fa, fb;
         load_row_frag(Ffw, row_of(0), lane, fa);
         for (int n0 = 0; n0 < p_in; n0 += 2 * kWaves) {
             if (row_of(n0) >= p_in) break;
-            load_row_frag(Ffw, row_of(n0 + kWaves), lane, fb);
+            fetch(row_of(n0 + kWaves), fb);
             row(fa, row_of(n0));
             if (row_of(n0 + kWaves) >= p_in) break;
-            load_row_frag(Ffw, row_of(n0 + 2 * kWaves), lane, fa);
+            fetch(row_of(n0 + 2 * kWaves), fa);
             row(fb, row_of(n0 + kWaves));
         }
     }
@@ -394,7 +432,6 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     {
         const double *Zt = tab.bz[basis][OP];
         const int t = lane & 15, kg = lane >> 4;
-        auto col_of = [&](int m0) { return m0 + (((m0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         auto load_z = [&](int m, double (&za)[2][8]) {
             const double *Z = Zt + big_z_off(m < kBigOrder ? m : kBigOrder - 1) + lane;
 #pragma unroll
@@ -407,15 +444,15 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
             const int ki = m < p_in ? (p_in - m + 3) / 4 : 0;
             double b[2][8];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    if (ks >= ki) break;
-                    const int i = m + 4 * ks + kg;
-                    const bool ok = i < p_in;
-                    const double v = X[(pos(ok ? i : m, m) + q) * kBT + t];
-                    b[q][ks] = ok ? v : 0.0;
-                }
+            for (int ks = 0; ks < 8; ++ks) {
+                if (ks >= ki) break;
+                const int i = m + 4 * ks + kg;
+                const bool ok = i < p_in;
+                const int r = ok ? i : m;
+                const double2 v = lds2(X + xe(r * (r + 1) / 2 + m, t));
+                b[0][ks] = ok ? v.x : 0.0;
+                b[1][ks] = ok ? v.y : 0.0;
+            }
             d4 res[2][2];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
@@ -438,36 +475,34 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
                 for (int j = 0; j < 4; ++j) {
                     const int o = m + 16 * mt + 4 * j + kg;
                     if (o >= p_out) continue;
-                    X[pos(o, m) * kBT + t] = res[0][mt][j];
-                    X[(pos(o, m) + 1) * kBT + t] = m ? res[1][mt][j] : 0.0;
+                    sts2(X + xe(o * (o + 1) / 2 + m, t), res[0][mt][j], m ? res[1][mt][j] : 0.0);
                 }
             }
         };
         double za[2][8], zb[2][8];
-        load_z(col_of(0), za);
+        load_z(row_of(0), za);
         for (int m0 = 0; m0 < p_out; m0 += 2 * kWaves) {
-            if (col_of(m0) >= p_out) break;
-            load_z(col_of(m0 + kWaves), zb);
-            column(za, col_of(m0));
-            if (col_of(m0 + kWaves) >= p_out) break;
-            load_z(col_of(m0 + 2 * kWaves), za);
-            column(zb, col_of(m0 + kWaves));
+            if (row_of(m0) >= p_out) break;
+            load_z(row_of(m0 + kWaves), zb);
+            column(za, row_of(m0));
+            if (row_of(m0 + kWaves) >= p_out) break;
+            load_z(row_of(m0 + 2 * kWaves), za);
+            column(zb, row_of(m0 + kWaves));
         }
     }
     __syncthreads();
 
     // ---- backward rotation, unscale ----
     {
-        auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
         auto row = [&](const RowFrag &f, int n) {
             d4 D[2][2], E[2][2];
-            swap_row(f, X, n, lane, D);
-            rotate_regs(L, n, lane, D, 2, -1.0);  // rotate by -beta
+            swap_row<false>(f, X, L, n, lane, D);
+            rotate_beta(L, n, lane, D, -1.0);
             swap_row_regs(f, n, D, E);
             if (fused)
-                store_row<Real>(aout, L, n, lane, E, nt);   // rotate by -alpha, unscale, store
+                store_row<Real>(aout, L, n, lane, E, nt);  // rotate by -alpha, unscale, store
             else
-                write_row(X, L, n, lane, E, 0, -1.0, L.scout);  // rotate by -alpha, unscale
+                write_row(X, L, n, lane, E, true);  // rotate by -alpha, unscale
         };
         RowFrag fa, fb;
         load_row_frag(Fbw, row_of(0), lane, fa);
@@ -488,9 +523,10 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
         for (int idx = tid; idx < npair * kBT; idx += kThreads) {
             const int t = idx & 15, p = idx >> 4;
             if (t >= nt) continue;
-            const int n = pair_degree(p), m = p - n * (n + 1) / 2;
+            const int nm = L.nm[p], n = nm >> 5, m = nm & 31;
             R2 *dp = reinterpret_cast<R2 *>(aout + L.ooff[t] + 2 * p);
-            double re = X[(2 * p) * kBT + t], im = m ? X[(2 * p + 1) * kBT + t] : 0.0;
+            const double2 v = lds2(X + xe(p, t));
+            double re = v.x, im = m ? v.y : 0.0;
             const int bad = L.bad[t];
             const bool ident = bad == 1 && OP != OP_M2L;
             if (bad) {
