@@ -134,7 +134,7 @@ void k_list_lpt(DevTables tab, ListArgs la)
                         pw.template rot<n>(xr, xi, 0, (Acc)1);
                         swap_row<Acc, n>(Pfw, xr, xi, yr, yi);
                         pw.template rot<n>(yr, yi, 1, (Acc)1);
-                        swap_row<Acc, n>(Pfw, yr, yi, xr, xi);
+                        swap_row<Acc, n>(launder(Pfw), yr, yi, xr, xi);
 #pragma unroll
                         for (int m = 0; m <= n; ++m) *reinterpret_cast<P2 *>(&Xt[solid_pos(n, m)]) = P2{xr[m], xi[m]};
                     }
@@ -206,7 +206,7 @@ void k_list_lpt(DevTables tab, ListArgs la)
                         }
                         swap_row<Acc, n>(Pbw, xr, xi, yr, yi);
                         pw.template rot<n>(yr, yi, 1, (Acc)-1);
-                        swap_row<Acc, n>(Pbw, yr, yi, xr, xi);
+                        swap_row<Acc, n>(launder(Pbw), yr, yi, xr, xi);
                         pw.template rot<n>(xr, xi, 0, (Acc)-1);
                         const Acc f = (OP == OP_M2M) ? ipow(R, n + 1) : ipow(s, n);
 #pragma unroll

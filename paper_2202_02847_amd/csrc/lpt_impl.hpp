@@ -244,6 +244,38 @@ __device__ __forceinline__ void swap_row(cptr<Acc> T, const Acc (&xr)[N + 1], co
     swap_pipe<Acc, N, 0>(T, cur, xr, xi, yr, yi);
 }
 
+// Coefficients c(o, k), k = m..PIN-1, of output degree o in column m of the unit z-shift.
+// In the paper basis (the FP64 tables) a coefficient depends on o + k alone (M2L:
+// (-1)^{o+m} (o+k)!, a Hankel matrix) or on o - k (M2M: (-1)^{o-k}/(o-k)!, L2L: 1/(k-o)!,
+// Toeplitz), so one short sequence serves every column: row 0 (M2L, L2L) or the last row
+// (M2M) of column 0 of the order-64 table holds it, and the few scalar-cache lines it spans
+// stay resident instead of one block of lines per column.  The normalised tables (FP32) are
+// read per column.  Entries outside the triangle of M2M / L2L are returned as 0 (unused).
+template <typename Real, typename Acc, int OP, int PIN, int M>
+__device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M])
+{
+    constexpr bool SEQ = std::is_same<Real, double>::value && std::is_same<Acc, double>::value;
+    constexpr int K = kZTableOrder;
+    const cptr<Acc> Z = launder(Z0);  // reloaded per output: only two outputs' entries live
+#pragma unroll
+    for (int k = M; k < PIN; ++k) {
+        if ((OP == OP_M2M && k > o) || (OP == OP_L2L && k < o)) {
+            c[k - M] = (Acc)0;
+        } else if constexpr (SEQ) {
+            if constexpr (OP == OP_M2L) {
+                const Acc v = Z[o + k];
+                c[k - M] = ((o + M) & 1) ? -v : v;
+            } else if constexpr (OP == OP_M2M) {
+                c[k - M] = Z[(K - 1) * K + (K - 1) - (o - k)];
+            } else {
+                c[k - M] = Z[k - o];
+            }
+        } else {
+            c[k - M] = Z[z_col_off(K, M) + (int64_t)(o - M) * (K - M) + (k - M)];
+        }
+    }
+}
+
 // Calls f(std::integral_constant<int, W>) for the wavefront index W = wave, so that each
 // wavefront runs straight-line code for its own share of rows / columns.
 template <int NW = 4, typename F>
@@ -359,7 +391,14 @@ void k_lpt(DevTables tab, TransArgs a)
     // another (a guarded load splits the code and the wait-count pass then serialises).
     constexpr int NP = 64 * (SIN / 2);
     constexpr int LIT = (NP + NT - 1) / NT;
-    constexpr bool PREFETCH = LIT * 2 * (int)sizeof(Real) / 4 <= 64;
+    // Where the 64 solids leave LDS room for one workgroup per CU (FP64 orders 13..16),
+    // every lane reads the rows of its own translation straight into registers in the
+    // forward rotation: no load phase through LDS, and the loads of one wavefront overlap
+    // the other wavefronts' arithmetic.  (Storing the output rows straight from the
+    // backward rotation as well measured no faster than the coalesced store phase, and
+    // non-temporal per-lane row stores were 2.5x slower: partial-line writes.)
+    constexpr bool DIRECT = NW == 8;
+    constexpr bool PREFETCH = !DIRECT && LIT * 2 * (int)sizeof(Real) / 4 <= 64;
     constexpr int CH = PREFETCH ? LIT : 16 * 4 / (int)sizeof(Real);  // loads per batch
     R2 pre[CH];
     Real prx = 0, pry = 0, prz = 1;
@@ -419,6 +458,8 @@ void k_lpt(DevTables tab, TransArgs a)
         const cptr<Acc> Pfw = launder(Pfw0), Pbw = launder(Pbw0), Z = launder(Z0);
         if constexpr (PREFETCH) {
             store_batch_lds(0);
+        } else if constexpr (DIRECT) {
+            load_shift(base, nt);
         } else {
 #pragma unroll 1
             for (int c0 = 0; c0 < NP; c0 += NT * CH) {
@@ -426,6 +467,12 @@ void k_lpt(DevTables tab, TransArgs a)
                 store_batch_lds(c0);
             }
             load_shift(base, nt);
+        }
+        // DIRECT: this lane's input solid (lanes past a partial block re-read the last one)
+        const Real *__restrict__ lin = gin;
+        if constexpr (DIRECT) {
+            const int tc = lane < nt ? lane : nt - 1;
+            lin = gin + (IDX ? gsrc[base + tc] : base + tc) * a.ld_in;
         }
         double x = (double)prx, y = (double)pry, z = (double)prz;
         if (lane >= nt) {
@@ -446,8 +493,16 @@ void k_lpt(DevTables tab, TransArgs a)
         const Acc s = (Acc)(g.valid == 1 ? g.s : 1.0);
         const Acc R = (Acc)(g.valid == 1 ? g.R : 1.0);
         Acc *Xt = X + lane * SP;
-        lds_barrier();
-        const bool bad_any = bad_flag != 0;
+        bool bad_any;
+        if constexpr (DIRECT) {
+            // every wavefront holds all 64 shifts: the block-wide test needs no LDS round trip,
+            // and nothing else of this block is in LDS yet (the previous block ended with a
+            // barrier after its store phase)
+            bad_any = __any(g.valid != 1 && lane < nt);
+        } else {
+            lds_barrier();
+            bad_any = bad_flag != 0;
+        }
         if constexpr (PREFETCH) {
             const int64_t nb = blk + gridDim.x;
             if (nb < nblk) {  // in flight during the transform of this block
@@ -462,11 +517,23 @@ void k_lpt(DevTables tab, TransArgs a)
             constexpr int n = decltype(nc)::value;
             if constexpr (row_owner(PIN, n, NW) == decltype(wc)::value) {
             Acc xr[n + 1], xi[n + 1], yr[n + 1], yi[n + 1];
+            if constexpr (DIRECT) {
+                __builtin_amdgcn_sched_barrier(0);  // one row's loads in flight at a time
+                R2 v[n + 1];
 #pragma unroll
-            for (int m = 0; m <= n; ++m) {
-                const P2 v = *reinterpret_cast<const P2 *>(&Xt[solid_pos(n, m)]);
-                xr[m] = v.x;
-                xi[m] = m ? v.y : (Acc)0;
+                for (int m = 0; m <= n; ++m) v[m] = *reinterpret_cast<const R2 *>(lin + solid_pos(n, m));
+#pragma unroll
+                for (int m = 0; m <= n; ++m) {
+                    xr[m] = (Acc)v[m].x;
+                    xi[m] = m ? (Acc)v[m].y : (Acc)0;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m <= n; ++m) {
+                    const P2 v = *reinterpret_cast<const P2 *>(&Xt[solid_pos(n, m)]);
+                    xr[m] = v.x;
+                    xi[m] = m ? v.y : (Acc)0;
+                }
             }
             // scale: M2L/M2M  M_n / |r|^{n+1};  L2L  L_n |r|^n   (eq. scaling)
             const Acc f = (OP == OP_L2L) ? ipow(R, n) : ipow(s, n + 1);
@@ -478,7 +545,7 @@ void k_lpt(DevTables tab, TransArgs a)
             pw.template rot<n>(xr, xi, 0, (Acc)1);
             swap_row<Acc, n>(Pfw, xr, xi, yr, yi);
             pw.template rot<n>(yr, yi, 1, (Acc)1);
-            swap_row<Acc, n>(Pfw, yr, yi, xr, xi);
+            swap_row<Acc, n>(launder(Pfw), yr, yi, xr, xi);
 #pragma unroll
             for (int m = 0; m <= n; ++m) *reinterpret_cast<P2 *>(&Xt[solid_pos(n, m)]) = P2{xr[m], xi[m]};
             }
@@ -502,19 +569,25 @@ void k_lpt(DevTables tab, TransArgs a)
                     ir[k] = v.x;
                     ii[k] = v.y;
                 }
-                constexpr int64_t zb = z_col_off(kZTableOrder, m);
+                // coefficients of output o + 1 are fetched while output o is summed
+                Acc cz[PIN - m];
+                z_fetch<Real, Acc, OP, PIN, m>(Z, m, cz);
 #pragma unroll
                 for (int o = m; o < POUT; ++o) {
+                    Acc nz[PIN - m];
+                    if (o + 1 < POUT) z_fetch<Real, Acc, OP, PIN, m>(Z, o + 1, nz);
                     Acc orr = 0, oi = 0;
 #pragma unroll
                     for (int k = m; k < PIN; ++k) {
                         if (OP == OP_M2M && k > o) continue;
                         if (OP == OP_L2L && k < o) continue;
-                        const Acc c = Z[zb + (int64_t)(o - m) * (kZTableOrder - m) + (k - m)];
-                        orr += c * ir[k];
-                        oi += c * ii[k];
+                        orr += cz[k - m] * ir[k];
+                        oi += cz[k - m] * ii[k];
                     }
                     *reinterpret_cast<P2 *>(&Xt[solid_pos(o, m)]) = P2{orr, oi};
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int k = 0; k < PIN - m; ++k) cz[k] = nz[k];
                 }
             }
         });
@@ -535,7 +608,7 @@ void k_lpt(DevTables tab, TransArgs a)
             }
             swap_row<Acc, n>(Pbw, xr, xi, yr, yi);
             pw.template rot<n>(yr, yi, 1, (Acc)-1);
-            swap_row<Acc, n>(Pbw, yr, yi, xr, xi);
+            swap_row<Acc, n>(launder(Pbw), yr, yi, xr, xi);
             pw.template rot<n>(xr, xi, 0, (Acc)-1);
             // unscale: M2L/L2L  L_n / |r|^n;  M2M  M_n |r|^{n+1}
             const Acc f = (OP == OP_M2M) ? ipow(R, n + 1) : ipow(s, n);

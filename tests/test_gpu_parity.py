@@ -116,6 +116,73 @@ def test_octree_full_size_sampled(ctx, orc, P):
     assert ctx.device_error() == 0
 
 
+@pytest.mark.parametrize("P", [13, 14, 15, 16])
+@pytest.mark.parametrize("op", ["m2l", "m2m", "l2l"])
+def test_one_block_per_cu_orders(ctx, orc, op, P):
+    """FP64 orders 13-16, where a block's 64 solids fill the CU's LDS and each lane reads its
+    input rows straight into registers.  Three full blocks and a ragged one; one full block
+    holds a zero shift (M2M/L2L identity, M2L error) among valid ones; then the same batch with
+    valid shifts, accumulated into an existing output, and gathered/scattered through index
+    arrays."""
+    torch, dev = torch_dev()
+    count = 3 * 64 + 9
+    print(f"[parity] one-block-per-CU op={op} P={P} count={count}", flush=True)
+    r, C = _inputs(orc, op, P, count, 700 + P, LENGTHS[op])
+    r[64 + 17] = 0.0  # inside block 1
+    live = np.ones(count, bool)
+    live[64 + 17] = False
+    ref = np.zeros((count, size(P)))
+    ref[live] = orc.translate_batch(op, P, P, r[live], C[live])
+    if op != "m2l":
+        ref[64 + 17] = C[64 + 17]
+        ref[64 + 17, [n * (n + 1) + 1 for n in range(P)]] = 0.0
+    ctx.device_error()  # clear
+    got, raw = run_batch(ctx, op, sh.SH_F64, P, P, r, C)
+    if op == "m2l":
+        assert np.isnan(raw[64 + 17]).all()
+        assert ctx.device_error() == sh.SH_ESHIFT
+    else:
+        assert ctx.device_error() == 0
+    ref_ld = np.zeros_like(ref)
+    ref_ld[live] = _ld_ref(op, P, P, r[live], C[live])
+    ref_ld[~live] = ref[~live]
+    if op == "m2l":
+        live_only = np.flatnonzero(live)
+        _check(got[live_only], ref[live_only], P, OUT_KIND[op], TOL[sh.SH_F64], f"{op} P={P}",
+               ref_ld[live_only])
+    else:
+        _check(got, ref, P, OUT_KIND[op], TOL[sh.SH_F64], f"{op} P={P}", ref_ld)
+
+    # valid shifts only, against the oracle
+    r2 = r.copy()
+    r2[64 + 17] = r[64 + 18]
+    plain, _ = run_batch(ctx, op, sh.SH_F64, P, P, r2, C)
+    sel = np.arange(64, 128)
+    _check(plain[sel], orc.translate_batch(op, P, P, r2[sel], C[sel]), P, OUT_KIND[op], TOL[sh.SH_F64],
+           f"{op} P={P} block 1", _ld_ref(op, P, P, r2[sel], C[sel]))
+    # accumulate: one FP64 addition per coefficient
+    base = plain * np.random.default_rng(P).uniform(-2.0, 2.0, plain.shape)
+    acc, _ = run_batch(ctx, op, sh.SH_F64, P, P, r2, C, flags=sh.SH_ACCUMULATE, out_init=base)
+    assert np.array_equal(acc, base + plain)
+
+    # indexed gather / scatter over pools: the same arithmetic as the batched call
+    npool = count + 40
+    rng = np.random.default_rng(P + 1)
+    src = rng.integers(0, count, count)
+    dst = rng.permutation(npool)[:count]
+    pool = torch.from_numpy(np.ascontiguousarray(C)).to(dev)
+    outp = torch.zeros((npool, size(P)), dtype=torch.float64, device=dev)
+    d_src = torch.from_numpy(src.astype(np.int64)).to(dev)
+    d_dst = torch.from_numpy(dst.astype(np.int64)).to(dev)
+    d_r = torch.from_numpy(r2).to(dev)
+    sh.sh_translate_indexed(ctx, op, sh.SH_F64, P, P, count, d_r, d_src, pool, size(P), d_dst, outp, size(P))
+    goti = outp.cpu().numpy()
+    gathered, _ = run_batch(ctx, op, sh.SH_F64, P, P, r2, C[src])
+    assert np.array_equal(goti[dst], gathered)
+    assert (goti[np.setdiff1d(np.arange(npool), dst)] == 0).all()
+    assert ctx.device_error() == 0
+
+
 @pytest.mark.parametrize("p_in,p_out", [(8, 8), (10, 10), (6, 9)])
 def test_naive_kernel(ctx, orc, p_in, p_out):
     r, C = _inputs(orc, "m2l", p_in, 45, 7 + p_in, (2.0, 4.0))
