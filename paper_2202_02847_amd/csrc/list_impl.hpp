@@ -42,10 +42,11 @@ void k_list_lpt(DevTables tab, ListArgs la)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
-    constexpr int fw = (OP == OP_L2L) ? SW_FL : SW_F;
-    constexpr int bw = (OP == OP_M2M) ? SW_F : SW_FL;
-    const cptr<Acc> Pfw0 = as_const(T::packed(tab, fw == SW_F ? 0 : 1));
-    const cptr<Acc> Pbw0 = as_const(T::packed(tab, bw == SW_F ? 0 : 1));
+    // both rotations read the M-side table; the L-side swaps (forward for L2L, backward for
+    // M2L and L2L) use it transposed
+    constexpr bool FT = OP == OP_L2L, BT = OP != OP_M2M;
+    const cptr<Acc> Pfw0 = as_const(T::packed(tab, 0));
+    const cptr<Acc> Pbw0 = Pfw0;
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
     const Real *__restrict__ ain = reinterpret_cast<const Real *>(la.arena_in);
     Real *__restrict__ aout = reinterpret_cast<Real *>(la.arena_out);
@@ -132,9 +133,9 @@ void k_list_lpt(DevTables tab, ListArgs la)
                             xi[m] *= f;
                         }
                         pw.template rot<n>(xr, xi, 0, (Acc)1);
-                        swap_row<Acc, n>(Pfw, xr, xi, yr, yi);
+                        swap_row_x<Acc, n, FT>(Pfw, xr, xi, yr, yi);
                         pw.template rot<n>(yr, yi, 1, (Acc)1);
-                        swap_row<Acc, n>(launder(Pfw), yr, yi, xr, xi);
+                        swap_row_x<Acc, n, FT>(launder(Pfw), yr, yi, xr, xi);
 #pragma unroll
                         for (int m = 0; m <= n; ++m) *reinterpret_cast<P2 *>(&Xt[solid_pos(n, m)]) = P2{xr[m], xi[m]};
                     }
@@ -166,9 +167,13 @@ void k_list_lpt(DevTables tab, ListArgs la)
                                     ii[k] = 0;
                                 }
                             }
-                            constexpr int64_t zb = z_col_off(kZTableOrder, m);
+                            // coefficients of output o + 1 fetched while output o is summed
+                            Acc cz[PB - m];
+                            z_fetch<Real, Acc, OP, PB, m>(Z, m, cz);
 #pragma unroll
                             for (int o = m; o < PB; ++o) {
+                                Acc nz[PB - m];
+                                if (o + 1 < PB) z_fetch<Real, Acc, OP, PB, m>(Z, o + 1, nz);
                                 if (o < p_out) {
                                     Acc orr = 0, oi = 0;
 #pragma unroll
@@ -176,13 +181,15 @@ void k_list_lpt(DevTables tab, ListArgs la)
                                         if (OP == OP_M2M && k > o) continue;
                                         if (OP == OP_L2L && k < o) continue;
                                         if (k < p_in) {
-                                            const Acc c = Z[zb + (int64_t)(o - m) * (kZTableOrder - m) + (k - m)];
-                                            orr += c * ir[k];
-                                            oi += c * ii[k];
+                                            orr += cz[k - m] * ir[k];
+                                            oi += cz[k - m] * ii[k];
                                         }
                                     }
                                     *reinterpret_cast<P2 *>(&Xt[solid_pos(o, m)]) = P2{orr, oi};
                                 }
+                                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                                for (int k = 0; k < PB - m; ++k) cz[k] = nz[k];
                             }
                         }
                     }
@@ -204,9 +211,9 @@ void k_list_lpt(DevTables tab, ListArgs la)
                             xr[m] = v.x;
                             xi[m] = m ? v.y : (Acc)0;
                         }
-                        swap_row<Acc, n>(Pbw, xr, xi, yr, yi);
+                        swap_row_x<Acc, n, BT>(Pbw, xr, xi, yr, yi);
                         pw.template rot<n>(yr, yi, 1, (Acc)-1);
-                        swap_row<Acc, n>(launder(Pbw), yr, yi, xr, xi);
+                        swap_row_x<Acc, n, BT>(launder(Pbw), yr, yi, xr, xi);
                         pw.template rot<n>(xr, xi, 0, (Acc)-1);
                         const Acc f = (OP == OP_M2M) ? ipow(R, n + 1) : ipow(s, n);
 #pragma unroll

@@ -276,6 +276,63 @@ __device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M])
     }
 }
 
+// The L-side swap of degree N from the M-side table.  The L-side real-part matrix is
+// F_L = D F^T D^{-1} (D = diag(2, 1, ..., 1), the corrected reading of the transposed matrices
+// of Section 3.4) and the imaginary-part matrix is G^T, so
+//   Re y = D F^T D^{-1} Re x,   Im y = G^T Im x,
+// computed as updates y += x_L * (packed row L of F, G) over L = 0..N: every output sums its
+// terms in the same (ascending) order as the product with the L-side table would, and the
+// factors 2 and 1/2 are exact, so the result is that product's.  One table then serves both
+// sides, halving the scalar-cache footprint of M2L (forward F, backward F_L).
+template <typename Acc, int N, int L>
+__device__ __forceinline__ void swapT_in(const Acc (&t)[N + 1], Acc xl_r, Acc xl_i, Acc (&yr)[N + 1],
+                                         Acc (&yi)[N + 1])
+{
+    int at = 0;
+#pragma unroll
+    for (int l = 0; l <= N; ++l)
+        if ((L + l + N) % 2 == 0) yr[l] += t[at++] * xl_r;
+    if (L > 0) {
+#pragma unroll
+        for (int l = 1; l <= N; ++l)
+            if ((L + l + N) % 2 == 1) yi[l] += t[at++] * xl_i;
+    }
+}
+
+template <typename Acc, int N, int L>
+__device__ __forceinline__ void swapT_pipe(cptr<Acc> T, Acc (&cur)[N + 1], const Acc (&xr)[N + 1],
+                                           const Acc (&xi)[N + 1], Acc (&yr)[N + 1], Acc (&yi)[N + 1])
+{
+    if constexpr (L <= N) {
+        Acc nxt[N + 1];
+        swap_fetch<Acc, N, L + 1>(T, nxt);
+        swapT_in<Acc, N, L>(cur, L == 0 ? xr[0] * (Acc)0.5 : xr[L], xi[L], yr, yi);
+        __builtin_amdgcn_sched_barrier(0);
+        swapT_pipe<Acc, N, L + 1>(T, nxt, xr, xi, yr, yi);
+    }
+}
+
+// TR = false: y = (F, G) x from the packed M-side table; TR = true: the L-side swap from the
+// same table (see swapT_in).
+template <typename Acc, int N, bool TR>
+__device__ __forceinline__ void swap_row_x(cptr<Acc> T, const Acc (&xr)[N + 1], const Acc (&xi)[N + 1],
+                                           Acc (&yr)[N + 1], Acc (&yi)[N + 1])
+{
+    if constexpr (!TR) {
+        swap_row<Acc, N>(T, xr, xi, yr, yi);
+    } else {
+#pragma unroll
+        for (int m = 0; m <= N; ++m) {
+            yr[m] = (Acc)0;
+            yi[m] = (Acc)0;
+        }
+        Acc cur[N + 1];
+        swap_fetch<Acc, N, 0>(T, cur);
+        swapT_pipe<Acc, N, 0>(T, cur, xr, xi, yr, yi);
+        yr[0] *= (Acc)2;
+    }
+}
+
 // Calls f(std::integral_constant<int, W>) for the wavefront index W = wave, so that each
 // wavefront runs straight-line code for its own share of rows / columns.
 template <int NW = 4, typename F>
@@ -372,10 +429,11 @@ void k_lpt(DevTables tab, TransArgs a)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
-    constexpr int fw = (OP == OP_L2L) ? SW_FL : SW_F;
-    constexpr int bw = (OP == OP_M2M) ? SW_F : SW_FL;
-    const cptr<Acc> Pfw0 = as_const(T::packed(tab, fw == SW_F ? 0 : 1));
-    const cptr<Acc> Pbw0 = as_const(T::packed(tab, bw == SW_F ? 0 : 1));
+    // both rotations read the M-side table; the L-side swaps (forward for L2L, backward for
+    // M2L and L2L) use it transposed
+    constexpr bool FT = OP == OP_L2L, BT = OP != OP_M2M;
+    const cptr<Acc> Pfw0 = as_const(T::packed(tab, 0));
+    const cptr<Acc> Pbw0 = Pfw0;
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
     const Real *__restrict__ rr = reinterpret_cast<const Real *>(a.r);
     const Real *__restrict__ gin = reinterpret_cast<const Real *>(a.in);
@@ -543,9 +601,9 @@ void k_lpt(DevTables tab, TransArgs a)
                 xi[m] *= f;
             }
             pw.template rot<n>(xr, xi, 0, (Acc)1);
-            swap_row<Acc, n>(Pfw, xr, xi, yr, yi);
+            swap_row_x<Acc, n, FT>(Pfw, xr, xi, yr, yi);
             pw.template rot<n>(yr, yi, 1, (Acc)1);
-            swap_row<Acc, n>(launder(Pfw), yr, yi, xr, xi);
+            swap_row_x<Acc, n, FT>(launder(Pfw), yr, yi, xr, xi);
 #pragma unroll
             for (int m = 0; m <= n; ++m) *reinterpret_cast<P2 *>(&Xt[solid_pos(n, m)]) = P2{xr[m], xi[m]};
             }
@@ -606,9 +664,9 @@ void k_lpt(DevTables tab, TransArgs a)
                 xr[m] = v.x;
                 xi[m] = m ? v.y : (Acc)0;
             }
-            swap_row<Acc, n>(Pbw, xr, xi, yr, yi);
+            swap_row_x<Acc, n, BT>(Pbw, xr, xi, yr, yi);
             pw.template rot<n>(yr, yi, 1, (Acc)-1);
-            swap_row<Acc, n>(launder(Pbw), yr, yi, xr, xi);
+            swap_row_x<Acc, n, BT>(launder(Pbw), yr, yi, xr, xi);
             pw.template rot<n>(xr, xi, 0, (Acc)-1);
             // unscale: M2L/L2L  L_n / |r|^n;  M2M  M_n |r|^{n+1}
             const Acc f = (OP == OP_M2M) ? ipow(R, n + 1) : ipow(s, n);
