@@ -78,6 +78,8 @@ class Oracle:
             "or_eval_m": (ct, [i32, P, P, P]),
             "or_eval_l": (ct, [i32, P, P, P]),
             "or_direct": (ct, [i64, P, P, P]),
+            "or_l2p": (None, [i32, P, P, P, P]),
+            "or_l2p_batch": (None, [i64, i32, P, i64, P, P, i64, P, i32]),
             "or_translate_batch": (None, [i32, i64, i32, i32, P, P, i64, P, i64, i32]),
             "or_p2m_batch": (None, [i64, i32, P, i64, P, P, P, i64, i32]),
             "or_p2l_batch": (None, [i64, i32, P, i64, P, P, P, i64, i32]),
@@ -188,6 +190,26 @@ class Oracle:
         L, Lp = self._arr(L)
         x, xp = self._arr(x)
         return self._lib.or_eval_l(P, cp, Lp, xp)
+
+    def l2p(self, P, centre, L, x):
+        """{Phi_L(x), grad Phi_L(x)} of one local expansion at one point."""
+        c, cp = self._arr(centre)
+        L, Lp = self._arr(L)
+        x, xp = self._arr(x)
+        out = np.zeros(4, self.dtype)
+        self._lib.or_l2p(P, cp, Lp, xp, out.ctypes.data_as(self._P))
+        return out
+
+    def l2p_batch(self, P, centres, pts, L, nthreads=1):
+        """Boxes of npts targets each: returns (count, npts, 4) = {Phi, grad Phi} per target."""
+        centres, cp = self._arr(np.reshape(centres, (-1, 3)))
+        count = centres.shape[0]
+        pts, pp = self._arr(np.reshape(pts, (count, -1, 3)))
+        npts = pts.shape[1]
+        L, Lp = self._arr(np.reshape(L, (count, -1)))
+        out = np.zeros((count, npts, 4), self.dtype)
+        self._lib.or_l2p_batch(count, P, cp, npts, pp, Lp, L.shape[1], out.ctypes.data_as(self._P), nthreads)
+        return out
 
     def direct(self, pts, q, x):
         pts, pp = self._arr(np.reshape(pts, (-1, 3)))

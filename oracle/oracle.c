@@ -23,7 +23,9 @@
  *       L'_k^l = sum_{n=k}^{p_in-1} sum_m L_n^m conj(R_{n-k}^{m-l}(r)),
  *     with r = (new centre) - (old centre), R_j^i = 0 for |i| > j;
  *   - evaluation of an M or L expansion (eq. MLexpansions) and the direct sum
- *     of eq. (nbody) with G = 1/|x - y|.
+ *     of eq. (nbody) with G = 1/|x - y|;
+ *   - L2P: the L expansion's potential and its gradient, each R_n^m differentiated by
+ *     the derivative identities of the harmonics (stated at or_l2p).
  *
  * Storage of a solid of order P (Section 2.1, Fig. 1): P(P+1) reals, row n (degree)
  * starting at n(n+1); Re C_n^m at n(n+1) + 2m, Im C_n^m at n(n+1) + 2m + 1,
@@ -272,6 +274,55 @@ real or_eval_l(int P, const real *centre, const real *L, const real *x)
     return acc;
 }
 
+/* R_n^m(d) for any integer m (zero when |m| > n or n < 0), from a table of R_n^m, m >= 0. */
+static void get_r(const real *R, int n, int m, real *re, real *im)
+{
+    if (n < 0 || m > n || -m > n) {
+        *re = 0;
+        *im = 0;
+        return;
+    }
+    get(R, n, m, re, im);
+}
+
+/*
+ * L2P: the potential Phi_L(x) = Re sum_{n<P} sum_{m=-n}^{n} L_n^m conj(R_n^m(x - x_B))
+ * (eq. MLexpansions) and its gradient, out = {Phi, dPhi/dx, dPhi/dy, dPhi/dz}.
+ * The gradient differentiates each R_n^m; for the harmonics defined by the Appendix
+ * recurrences the derivatives are
+ *   d/dz R_n^m = R_{n-1}^m,
+ *   d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1}) / 2,
+ *   d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1}) / 2.
+ */
+void or_l2p(int P, const real *centre, const real *L, const real *x, real *out)
+{
+    real d[3] = {x[0] - centre[0], x[1] - centre[1], x[2] - centre[2]};
+    real *R = (real *)malloc(sizeof(real) * (size_t)P * (P + 1));
+    or_regular(d, P, R);
+    real phi = 0, gx = 0, gy = 0, gz = 0;
+    for (int n = 0; n < P; ++n)
+        for (int m = -n; m <= n; ++m) {
+            real lr, li, ar, ai, br, bi, cr, ci;
+            get(L, n, m, &lr, &li);
+            get(R, n, m, &ar, &ai);
+            phi += lr * ar + li * ai; /* Re(L conj(R)) */
+            get_r(R, n - 1, m - 1, &ar, &ai);
+            get_r(R, n - 1, m + 1, &br, &bi);
+            get_r(R, n - 1, m, &cr, &ci);
+            /* dR/dx = (A - B)/2, dR/dy = i (A + B)/2 = (-(ai + bi) + i (ar + br))/2, dR/dz = C */
+            real xr = (ar - br) / 2, xi = (ai - bi) / 2;
+            real yr = -(ai + bi) / 2, yi = (ar + br) / 2;
+            gx += lr * xr + li * xi;
+            gy += lr * yr + li * yi;
+            gz += lr * cr + li * ci;
+        }
+    free(R);
+    out[0] = phi;
+    out[1] = gx;
+    out[2] = gy;
+    out[3] = gz;
+}
+
 /* u(x) = sum_j q_j / |x - y_j|  (eq. nbody with G = 1/|x-y|) */
 real or_direct(int64_t npts, const real *pts, const real *q, const real *x)
 {
@@ -321,6 +372,17 @@ void or_p2l_batch(int64_t count, int P, const real *centres, int64_t npts, const
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
     for (int64_t c = 0; c < count; ++c)
         or_p2l(P, centres + 3 * c, npts, pts + 3 * npts * c, q + npts * c, L + c * ldL);
+}
+
+/* L2P of many boxes: box c has npts targets at pts + 3*npts*c and its local expansion at
+ * L + c*ldL; target j of box c writes out[4*(npts*c + j) .. +3] = {Phi, grad Phi}. */
+void or_l2p_batch(int64_t count, int P, const real *centres, int64_t npts, const real *pts,
+                  const real *L, int64_t ldL, real *out, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t c = 0; c < count; ++c)
+        for (int64_t j = 0; j < npts; ++j)
+            or_l2p(P, centres + 3 * c, L + c * ldL, pts + 3 * (npts * c + j), out + 4 * (npts * c + j));
 }
 
 int or_real_size(void) { return (int)sizeof(real); }

@@ -377,6 +377,58 @@ def pin_eval_m_far_field(o):
     return worst, 1e-9
 
 
+def pin_l2p_gradient_finite_difference(o):
+    """L2P returns the potential of eq. MLexpansions (the pinned eval_l) and its gradient:
+    a fourth-order central difference of eval_l (error O(h^4), the expansion is a
+    polynomial) agrees with the returned gradient; the batch form equals the single calls."""
+    rng = _rng(52)
+    err = 0.0
+    h = 1e-3
+    for P in (1, 2, 6, 13):
+        L = _random_solid(rng, P, decay=0.9)
+        c = rng.uniform(-0.2, 0.2, 3)
+        for _ in range(3):
+            x = c + rng.uniform(-0.5, 0.5, 3)
+            out = o.l2p(P, c, L, x)
+            phi = o.eval_l(P, c, L, x)
+            fd = np.zeros(3)
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = h
+                f = [o.eval_l(P, c, L, x + k * e) for k in (-2, -1, 1, 2)]
+                fd[a] = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+            scale = max(1e-3, float(np.max(np.abs(fd))), abs(phi))
+            err = max(err, abs(float(out[0]) - phi) / scale, float(np.max(np.abs(out[1:] - fd))) / scale)
+    centres = rng.uniform(-0.2, 0.2, (3, 3))
+    pts = centres[:, None, :] + rng.uniform(-0.4, 0.4, (3, 5, 3))
+    Ls = np.stack([_random_solid(rng, 7) for _ in range(3)])
+    ob = o.l2p_batch(7, centres, pts, Ls, nthreads=2)
+    for i in range(3):
+        for j in range(5):
+            err = max(err, _rel(ob[i, j], o.l2p(7, centres[i], Ls[i], pts[i, j])))
+    return err, 1e-8
+
+
+def pin_l2p_vs_direct_field(o):
+    """P2L of a far cluster, then L2P, reproduces the direct potential sum q_j/|x - y_j| and
+    its gradient -sum q_j (x - y_j)/|x - y_j|^3 (eq. nbody), to the truncation accuracy."""
+    rng = _rng(53)
+    P = 20
+    pts, q = _cluster(rng, 20, centre=_unit(rng) * 3.5)
+    L = o.p2l(P, [0, 0, 0], pts, q)
+    worst = 0.0
+    for _ in range(4):
+        t = _unit(rng) * 0.3
+        d = t[None, :] - pts
+        r = np.linalg.norm(d, axis=1)
+        phi = float(np.sum(q / r))
+        grad = -np.sum((q / r ** 3)[:, None] * d, axis=0)
+        out = o.l2p(P, [0, 0, 0], L, t)
+        scale = float(np.max(np.abs(grad)))
+        worst = max(worst, abs(float(out[0]) - phi) / abs(phi), float(np.max(np.abs(out[1:] - grad))) / scale)
+    return worst, 1e-8
+
+
 PINS = [
     pin_regular_closed_form,
     pin_singular_closed_form,
@@ -397,4 +449,6 @@ PINS = [
     pin_l2l_after_m2l_vs_direct,
     pin_p2l_closed_form_and_near_field,
     pin_eval_m_far_field,
+    pin_l2p_gradient_finite_difference,
+    pin_l2p_vs_direct_field,
 ]
