@@ -265,6 +265,32 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
             "staging_peak_mb": round(st["staging_peak_bytes"] / 2 ** 20, 1)}
 
 
+def l2p_flops_per_target(P):
+    """Flops of the column-streamed L2P per target: for each of the P(P+1)/2 harmonics
+    R_k^j, 6 for its recurrence, 4 for the potential term and 12 for the three gradient
+    terms (reciprocals of the recurrence constants not counted)."""
+    return 22 * P * (P + 1) // 2
+
+
+def run_l2p(sh, ctx, torch, dev, P=10, boxes=1 << 14, npts=64, reps=10):
+    """L2P (potential and gradient) of 2^14 boxes x 64 targets at P = 10: leaves of a
+    uniform octree with 64 particles each, targets uniform in the box, local expansions
+    of decaying random coefficients."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(10)
+    S = solid(P)
+    c = torch.rand((boxes, 3), generator=g, device=dev, dtype=torch.float64)
+    t = c[:, None, :] + torch.rand((boxes, npts, 3), generator=g, device=dev, dtype=torch.float64) - 0.5
+    L = torch.randn((boxes, S), generator=g, device=dev, dtype=torch.float64) * 1e-2
+    out = torch.empty((boxes, npts, 4), device=dev, dtype=torch.float64)
+    s = time_launch(torch, lambda: sh.sh_l2p_batch_f64(ctx, P, boxes, c, npts, t, L, S, out), reps)
+    n = boxes * npts
+    flops = l2p_flops_per_target(P) * n / s
+    return {"targets_per_s": n / s, "ms": round(s * 1e3, 4), "boxes": boxes, "targets_per_box": npts,
+            "flops_per_target": l2p_flops_per_target(P), "frac_fp64_vector": round(flops / 78.6e12, 4),
+            "bytes_per_target": 56}
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -453,6 +479,9 @@ def main():
             log(f"[bench] mixed-order list {name}")
             extra[f"mixed_list_{name}"] = run_mixed(sh, ctx, torch, dev, dt)
             torch.cuda.empty_cache()
+        log("[bench] L2P P=10")
+        extra["l2p_p10_f64"] = run_l2p(sh, ctx, torch, dev)
+        torch.cuda.empty_cache()
         for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
             log(f"[bench] extra P={PP} n={nn_}")
             J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)

@@ -350,6 +350,20 @@ sh_status sh_p2m_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double
                            int64_t npts, const double *pts, const double *q, double *M,
                            int64_t ldM, void *hip_stream);
 
+/* L2P on the device: the potential Phi_L(x) = Re sum_{n<P} sum_m L_n^m conj(R_n^m(x - c))
+ * of a local expansion (eq. MLexpansions) and its gradient, R by the Appendix recurrence
+ * and differentiated by the identities d/dz R_n^m = R_{n-1}^m,
+ * d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1})/2, d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1})/2.
+ * `count` boxes of `npts` targets each: box c has centre centres[3c..], local expansion
+ * L + c*ldL (order P, Im L_n^0 ignored) and targets pts[3*npts*c ..]; target j of box c
+ * writes out[4*(npts*c + j) .. +3] = {Phi, dPhi/dx, dPhi/dy, dPhi/dz} (the field of the
+ * potential sum q/|x - y| is minus the gradient).  flags: 0 or SH_ACCUMULATE.  FP64,
+ * device pointers owned by the caller, stream-ordered.  Errors: SH_EINVAL (null pointer,
+ * negative count, ldL < P(P+1), unknown flags), SH_EORDER, SH_EDEVICE. */
+sh_status sh_l2p_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double *centres,
+                           int64_t npts, const double *pts, const double *L, int64_t ldL,
+                           double *out, unsigned flags, void *hip_stream);
+
 /* ---------------- host-only helpers (no device needed) ----------------
  * Dense (n+1)x(n+1) row-major swap matrix of degree n (0 <= n < SH_MAX_ORDER), rounded
  * once from exact arithmetic.  which: 0 = F (M side, real parts), 1 = G (M side,

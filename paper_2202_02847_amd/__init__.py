@@ -55,6 +55,7 @@ _SIGS = {
     "sh_translate_indexed": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _vp, _c_i64, _vp, _vp, _c_i64, _c_u32, _vp]),
     "sh_m2l_naive_batch_f64": (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
     "sh_p2m_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _vp, _c_i64, _vp]),
+    "sh_l2p_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_u32, _vp]),
     "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
     "sh_normalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
     "sh_denormalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
@@ -244,6 +245,11 @@ sh_m2l_naive_batch_f64 = _make_batch("sh_m2l_naive_batch_f64")
 def sh_p2m_batch_f64(ctx, P, count, centres, npts, pts, q, M, ldM, stream=None):
     _check(lib().sh_p2m_batch_f64(_h(ctx), P, count, _ptr(centres), npts, _ptr(pts), _ptr(q), _ptr(M), ldM,
                                   _stream(stream)), "sh_p2m_batch_f64")
+
+
+def sh_l2p_batch_f64(ctx, P, count, centres, npts, pts, L, ldL, out, flags=0, stream=None):
+    _check(lib().sh_l2p_batch_f64(_h(ctx), P, count, _ptr(centres), npts, _ptr(pts), _ptr(L), ldL, _ptr(out),
+                                  flags, _stream(stream)), "sh_l2p_batch_f64")
 
 
 def sh_swap_matrix_f64(n: int, which: int, normalised: bool = False) -> np.ndarray:

@@ -401,6 +401,23 @@ sh_status sh_p2m_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double
                : SH_EDEVICE;
 }
 
+sh_status sh_l2p_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double *centres, int64_t npts,
+                           const double *pts, const double *L, int64_t ldL, double *out, unsigned flags,
+                           void *hip_stream)
+{
+    if (!ctx || count < 0 || npts < 0 || (flags & ~SH_ACCUMULATE)) return SH_EINVAL;
+    if (P < 1 || P > ctx->max_order) return SH_EORDER;
+    if (ldL < (int64_t)P * (P + 1)) return SH_EINVAL;
+    if (count == 0 || npts == 0) return SH_OK;
+    if (!centres || !pts || !L || !out) return SH_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    return shfmm::launch_l2p(P, count, centres, npts, pts, L, ldL, out, flags,
+                             reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess
+               ? SH_OK
+               : SH_EDEVICE;
+}
+
 sh_status sh_swap_matrix_f64(int n, int which, int normalised, double *out)
 {
     if (!out || which < 0 || which > 3) return SH_EINVAL;

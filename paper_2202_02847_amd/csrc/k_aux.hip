@@ -2,12 +2,17 @@
 //   * the direct O(P^4) double-height M2L (eq. m2lkernels, right), the baseline the paper
 //     measures its scheme against (Section 4), with S by the Appendix recurrences;
 //   * P2M (eq. MLexpansions: M_n^m = sum_j q_j R_n^m(y_j - x_A)), R by the Appendix
-//     recurrences, used to build multipole inputs on the device.
+//     recurrences, used to build multipole inputs on the device;
+//   * L2P: the potential of a local expansion (eq. MLexpansions) and its gradient at
+//     target points.
 #include "kernels.hpp"
 
 namespace shfmm {
 
 namespace {
+
+// read-only device memory addressed wave-uniformly: loads through the scalar cache
+using lpt_cptr = const __attribute__((address_space(4))) double *;
 
 __device__ __forceinline__ int tri_row_aux(int c)
 {
@@ -157,6 +162,93 @@ __global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *
     }
 }
 
+// L2P: one lane per target, the 64 lanes of a wavefront on targets of one box, so that the
+// box's local expansion is read through the scalar cache.  R_k^j(x - c) is generated
+// column by column (j) by the Appendix recurrences and used at once:
+//   Phi    = Re sum_{k,j} conj(R_k^j) L_k^j,
+//   grad   = Re sum_{k,j} conj(R_k^j) (X, Y, Z),  X = (L_{k+1}^{j+1} - L_{k+1}^{j-1}) / 2,
+//            Y = -i (L_{k+1}^{j+1} + L_{k+1}^{j-1}) / 2,  Z = L_{k+1}^j,
+// which is the derivative identities of the harmonics (d/dz R_n^m = R_{n-1}^m,
+// d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1}) / 2, d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1}) / 2)
+// gathered per R_k^j instead of per L_n^m.  The term of -j equals the conjugate of that of
+// j, so columns j > 0 count twice.  Im L_n^0 is ignored (read as 0).
+__global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunks, const double *centres,
+                                             int64_t npts, const double *pts, const double *Lpool,
+                                             int64_t ldL, double *out, unsigned flags)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t ntask = count * chunks;
+    const bool acc = (flags & 1u) != 0;
+    for (int64_t task = (int64_t)blockIdx.x * 4 + wave; task < ntask; task += (int64_t)gridDim.x * 4) {
+        const int64_t c = task / chunks;
+        const int64_t j0 = (task - c * chunks) * 64 + lane;
+        const bool act = j0 < npts;
+        const int64_t t = c * npts + (act ? j0 : 0);
+        const lpt_cptr Lc = (lpt_cptr)(Lpool + c * ldL);
+        const lpt_cptr cc = (lpt_cptr)(centres + 3 * c);
+        const double x = pts[3 * t] - cc[0], y = pts[3 * t + 1] - cc[1], z = pts[3 * t + 2] - cc[2];
+        const double r2 = x * x + y * y + z * z;
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        double dr = 1.0, di = 0.0;  // R_j^j
+        for (int j = 0; j < P; ++j) {
+            if (j > 0) {
+                const double f = 0.5 / (double)j;
+                const double nr = (x * dr - y * di) * f, ni = (x * di + y * dr) * f;
+                dr = nr;
+                di = ni;
+            }
+            double ar = dr, ai = di, br = 0.0, bi = 0.0;  // R_k^j, R_{k-1}^j
+            double cp = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+            for (int k = j; k < P; ++k) {
+                if (k > j) {
+                    const double inv = 1.0 / ((double)k * k - (double)j * j);
+                    const double tz = (double)(2 * k - 1) * z;
+                    const double nr = (tz * ar - r2 * br) * inv, ni = (tz * ai - r2 * bi) * inv;
+                    br = ar;
+                    bi = ai;
+                    ar = nr;
+                    ai = ni;
+                }
+                const int64_t pk = (int64_t)k * (k + 1) + 2 * j;
+                cp += ar * Lc[pk] + (j ? ai * Lc[pk + 1] : 0.0);
+                if (k + 1 < P) {
+                    const int64_t pz = (int64_t)(k + 1) * (k + 2) + 2 * j;
+                    const double zr = Lc[pz], zi = j ? Lc[pz + 1] : 0.0;
+                    const double ur = Lc[pz + 2], ui = Lc[pz + 3];  // L_{k+1}^{j+1}
+                    double vr, vi;                                   // L_{k+1}^{j-1}
+                    if (j == 0) {
+                        vr = -ur;
+                        vi = ui;
+                    } else {
+                        vr = Lc[pz - 2];
+                        vi = (j > 1) ? Lc[pz - 1] : 0.0;
+                    }
+                    cx += 0.5 * (ar * (ur - vr) + ai * (ui - vi));
+                    cy += 0.5 * (ar * (ui + vi) - ai * (ur + vr));
+                    cz += ar * zr + ai * zi;
+                }
+            }
+            const double w = j ? 2.0 : 1.0;
+            phi += w * cp;
+            gx += w * cx;
+            gy += w * cy;
+            gz += w * cz;
+        }
+        if (act) {
+            double *o = out + 4 * t;
+            if (acc) {
+                phi += o[0];
+                gx += o[1];
+                gy += o[2];
+                gz += o[3];
+            }
+            *reinterpret_cast<double2 *>(o) = double2{phi, gx};
+            *reinterpret_cast<double2 *>(o + 2) = double2{gy, gz};
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_m2l_naive(const TransArgs &a, hipStream_t s)
@@ -176,6 +268,18 @@ hipError_t launch_p2m(int P, int64_t count, const double *centres, int64_t npts,
     const size_t smem = (size_t)P * (P + 1) * sizeof(double);
     const int64_t grid64 = count < (1 << 20) ? count : (1 << 20);
     hipLaunchKernelGGL(k_p2m, dim3((unsigned)grid64), dim3(64), smem, s, P, count, centres, npts, pts, q, M, ldM);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2p(int P, int64_t count, const double *centres, int64_t npts, const double *pts,
+                      const double *L, int64_t ldL, double *out, unsigned flags, hipStream_t s)
+{
+    if (count <= 0 || npts <= 0) return hipSuccess;
+    const int64_t chunks = (npts + 63) / 64;
+    const int64_t blocks = (count * chunks + 3) / 4;
+    const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
+    hipLaunchKernelGGL(k_l2p, dim3((unsigned)grid64), dim3(256), 0, s, P, count, chunks, centres, npts, pts, L, ldL,
+                       out, flags);
     return hipGetLastError();
 }
 

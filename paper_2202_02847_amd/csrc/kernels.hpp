@@ -119,5 +119,9 @@ hipError_t launch_m2l_naive(const TransArgs &a, hipStream_t s);
 // Device P2M (FP64).
 hipError_t launch_p2m(int P, int64_t count, const double *centres, int64_t npts,
                       const double *pts, const double *q, double *M, int64_t ldM, hipStream_t s);
+// L2P: potential and gradient of the local expansions of `count` boxes at their `npts`
+// targets each; out holds 4 doubles per target (flags bit 0: accumulate).
+hipError_t launch_l2p(int P, int64_t count, const double *centres, int64_t npts, const double *pts,
+                      const double *L, int64_t ldL, double *out, unsigned flags, hipStream_t s);
 
 }  // namespace shfmm

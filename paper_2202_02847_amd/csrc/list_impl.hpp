@@ -42,11 +42,12 @@ void k_list_lpt(DevTables tab, ListArgs la)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
-    // both rotations read the M-side table; the L-side swaps (forward for L2L, backward for
-    // M2L and L2L) use it transposed
-    constexpr bool FT = OP == OP_L2L, BT = OP != OP_M2M;
-    const cptr<Acc> Pfw0 = as_const(T::packed(tab, 0));
-    const cptr<Acc> Pbw0 = Pfw0;
+    // L-side swaps (forward for L2L, backward for M2L and L2L): from the L-side table, or
+    // from the M-side table read transposed (lpt_transposed_l)
+    constexpr bool TL = lpt_transposed_l<Acc, PB>();
+    constexpr bool FT = TL && OP == OP_L2L, BT = TL && OP != OP_M2M;
+    const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
+    const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
     const Real *__restrict__ ain = reinterpret_cast<const Real *>(la.arena_in);
     Real *__restrict__ aout = reinterpret_cast<Real *>(la.arena_out);

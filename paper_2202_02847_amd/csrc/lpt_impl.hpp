@@ -406,6 +406,16 @@ constexpr bool lpt_hold_powers()
     return sizeof(Acc) == 4 ? PM <= 12 : PM <= 6;
 }
 
+// Whether the L-side swaps read the M-side table transposed (swap_row_x) instead of the
+// L-side table.  Measured on MI355X (FP64 M2L, 2^20 translations): at order 10 the L-side
+// table is faster (0.385 vs 0.468 ms); from order 12 one table in the scalar cache wins
+// (P = 12: 0.675 vs 0.690 ms, P = 16: 1.41 vs 1.48 ms).
+template <typename Acc, int PM>
+constexpr bool lpt_transposed_l()
+{
+    return sizeof(Acc) == 8 && PM >= 12;
+}
+
 // IDX: translations gather their input from the index array src and scatter to dst
 // (indexed pools); otherwise translation i of the call uses solid i of in / out.
 template <typename Real, typename Acc, int OP, int PIN, int POUT, bool IDX>
@@ -429,11 +439,12 @@ void k_lpt(DevTables tab, TransArgs a)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
-    // both rotations read the M-side table; the L-side swaps (forward for L2L, backward for
-    // M2L and L2L) use it transposed
-    constexpr bool FT = OP == OP_L2L, BT = OP != OP_M2M;
-    const cptr<Acc> Pfw0 = as_const(T::packed(tab, 0));
-    const cptr<Acc> Pbw0 = Pfw0;
+    // L-side swaps (forward for L2L, backward for M2L and L2L): from the L-side table, or
+    // from the M-side table read transposed (lpt_transposed_l)
+    constexpr bool TL = lpt_transposed_l<Acc, PM>();
+    constexpr bool FT = TL && OP == OP_L2L, BT = TL && OP != OP_M2M;
+    const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
+    const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
     const Real *__restrict__ rr = reinterpret_cast<const Real *>(a.r);
     const Real *__restrict__ gin = reinterpret_cast<const Real *>(a.in);

@@ -1,0 +1,147 @@
+"""GPU parity of L2P (potential and gradient of local expansions at target points)
+against the CPU oracle, through the C ABI.
+
+Metric (per target): max |got - ref| over {Phi, dPhi/dx, dPhi/dy, dPhi/dz} divided by
+max |ref| of the same target.  Bound 1e-12 (FP64): the evaluation sums O(P^2) terms of
+a convergent expansion (targets inside the box, sources well separated), each rounded a
+few times, so the error stays within a few hundred ulps of the largest component.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2202_02847_amd as sh
+from paper_2202_02847_amd import workloads as wl
+from gpu_util import torch_dev
+from refmath import size
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sh.Context(max_order=32, device=0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+def _case(orc, P, count, npts, seed, im0_garbage=True):
+    """Boxes of half-width 0.5 about centres near the origin; each local expansion is the
+    P2L of a 20-point cluster about 3 box-widths away; targets uniform in the box."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-0.1, 0.1, (count, 3))
+    src, q = wl.clusters(rng, count, 20)
+    far = wl.directions(rng, count) * 3.0
+    src = src + (centres + far)[:, None, :]
+    L = orc.p2l_batch(P, centres, src, q, nthreads=8)
+    tgt = centres[:, None, :] + rng.uniform(-0.5, 0.5, (count, npts, 3))
+    ref = orc.l2p_batch(P, centres, tgt, L, nthreads=8)
+    if im0_garbage:
+        # Im L_n^0 is ignored on input: fill it with noise on the device copy only
+        L = L.copy()
+        L[:, [n * (n + 1) + 1 for n in range(P)]] = rng.normal(size=(count, P))
+    return centres, tgt, L, ref
+
+
+def _run(ctx, P, centres, tgt, L, flags=0, out_init=None, ldL=None):
+    torch, dev = torch_dev()
+    count, npts = tgt.shape[0], tgt.shape[1]
+    ldL = ldL or L.shape[1]
+    Lp = np.zeros((count, ldL))
+    Lp[:, : L.shape[1]] = L
+    d_c = torch.from_numpy(np.ascontiguousarray(centres)).to(dev)
+    d_t = torch.from_numpy(np.ascontiguousarray(tgt)).to(dev)
+    d_L = torch.from_numpy(Lp).to(dev)
+    if out_init is None:
+        d_o = torch.full((count, npts, 4), np.nan, dtype=torch.float64, device=dev)
+    else:
+        d_o = torch.from_numpy(np.ascontiguousarray(out_init)).to(dev)
+    sh.sh_l2p_batch_f64(ctx, P, count, d_c, npts, d_t, d_L, ldL, d_o, flags)
+    torch.cuda.synchronize()
+    return d_o.cpu().numpy()
+
+
+def _err(got, ref):
+    scale = np.max(np.abs(ref), axis=-1)
+    return float(np.max(np.max(np.abs(got - ref), axis=-1) / scale))
+
+
+# targets per box: one lane, a ragged wavefront, exactly one, several with a ragged tail
+@pytest.mark.parametrize("P,count,npts", [(1, 7, 5), (2, 9, 64), (10, 23, 70), (10, 5, 200), (16, 11, 33),
+                                          (24, 4, 129), (30, 3, 64), (31, 2, 1)])
+def test_l2p_matches_oracle(ctx, orc, P, count, npts):
+    centres, tgt, L, ref = _case(orc, P, count, npts, seed=100 + P * 7 + npts)
+    got = _run(ctx, P, centres, tgt, L)
+    assert np.isfinite(got).all()
+    assert _err(got, ref) <= TOL
+
+
+def test_l2p_accumulate_and_stride(ctx, orc):
+    P, count, npts = 12, 6, 90
+    centres, tgt, L, ref = _case(orc, P, count, npts, seed=7)
+    rng = np.random.default_rng(8)
+    init = rng.normal(size=(count, npts, 4))
+    got = _run(ctx, P, centres, tgt, L, flags=sh.SH_ACCUMULATE, out_init=init, ldL=size(P) + 6)
+    assert _err(got - init, ref) <= 1e-11
+
+
+def test_l2p_target_at_centre(ctx, orc):
+    """x = c: only L_0^0 and the degree-1 row contribute (R_0^0 = 1, R_n^m(0) = 0 else)."""
+    P, count = 8, 3
+    centres, _, L, _ = _case(orc, P, count, 1, seed=9)
+    tgt = centres[:, None, :].copy()
+    got = _run(ctx, P, centres, tgt, L)
+    ref = orc.l2p_batch(P, centres, tgt, L)
+    assert _err(got, ref) <= TOL
+    # Phi = L_0^0, dPhi/dx = Re L_1^1, dPhi/dy = Im L_1^1, dPhi/dz = Re L_1^0 (R_1^1 = (x + iy)/2, R_1^0 = z)
+    for c in range(count):
+        for k, idx in ((0, 0), (1, 4), (2, 5), (3, 2)):
+            assert abs(got[c, 0, k] - L[c, idx]) <= 1e-15 * max(1.0, abs(L[c, idx])), (c, k)
+
+
+def test_l2p_empty_and_errors(ctx):
+    torch, dev = torch_dev()
+    out = torch.full((4, 4), 3.0, dtype=torch.float64, device=dev)
+    x = torch.zeros((4, 3), dtype=torch.float64, device=dev)
+    L = torch.zeros((1, 110), dtype=torch.float64, device=dev)
+    sh.sh_l2p_batch_f64(ctx, 10, 0, x, 4, x, L, 110, out)
+    sh.sh_l2p_batch_f64(ctx, 10, 1, x, 0, x, L, 110, out)
+    torch.cuda.synchronize()
+    assert bool((out == 3.0).all())
+    with pytest.raises(sh.ShError):
+        sh.sh_l2p_batch_f64(ctx, 10, 1, x, 4, x, L, 100, out)  # ldL < P(P+1)
+    with pytest.raises(sh.ShError):
+        sh.sh_l2p_batch_f64(ctx, 33, 1, x, 4, x, L, 33 * 34, out)  # order above the context's
+    with pytest.raises(sh.ShError):
+        sh.sh_l2p_batch_f64(ctx, 10, 1, x, 4, x, L, 110, out, flags=4)  # unknown flag
+
+
+def test_l2p_full_size_sampled(ctx, orc):
+    """The benchmark's L2P workload (2^14 boxes of 64 targets, P = 10): a sample of targets
+    against the oracle, and the potential matching the direct sum to the truncation error."""
+    torch, dev = torch_dev()
+    P, count, npts = 10, 1 << 14, 64
+    rng = np.random.default_rng(21)
+    centres = rng.uniform(-0.1, 0.1, (count, 3))
+    tgt = centres[:, None, :] + rng.uniform(-0.5, 0.5, (count, npts, 3))
+    L = np.zeros((count, size(P)))
+    sample = rng.choice(count, 64, replace=False)
+    src, q = wl.clusters(rng, 64, 20)
+    src = src + (centres[sample] + wl.directions(rng, 64) * 3.0)[:, None, :]
+    L[sample] = orc.p2l_batch(P, centres[sample], src, q, nthreads=8)
+    got = _run(ctx, P, centres, tgt, L)
+    ref = orc.l2p_batch(P, centres[sample], tgt[sample], L[sample], nthreads=8)
+    assert _err(got[sample], ref) <= TOL
+    rest = np.setdiff1d(np.arange(count), sample)
+    assert bool((got[rest] == 0.0).all())
+    # truncation check on one box: the P = 10 expansion of a cluster 3 box-widths away
+    d = tgt[sample[0]][:, None, :] - src[0][None, :, :]
+    direct = np.sum(q[0][None, :] / np.linalg.norm(d, axis=2), axis=1)
+    assert float(np.max(np.abs(got[sample[0], :, 0] - direct)) / np.max(np.abs(direct))) < 1e-3
