@@ -79,6 +79,8 @@ class Oracle:
             "or_eval_l": (ct, [i32, P, P, P]),
             "or_direct": (ct, [i64, P, P, P]),
             "or_l2p": (None, [i32, P, P, P, P]),
+            "or_m2l_single": (None, [i32, P, P, P]),
+            "or_m2l_single_batch": (None, [i64, i32, P, P, i64, P, i64, i32]),
             "or_l2p_batch": (None, [i64, i32, P, i64, P, P, i64, P, i32]),
             "or_translate_batch": (None, [i32, i64, i32, i32, P, P, i64, P, i64, i32]),
             "or_p2m_batch": (None, [i64, i32, P, i64, P, P, P, i64, i32]),
@@ -159,6 +161,24 @@ class Oracle:
 
     def m2l(self, p_in, p_out, r, M):
         return self._tr(self._lib.or_m2l, p_in, p_out, r, M)
+
+    def m2l_single(self, P, r, M):
+        """Single-height M2L (eq. m2lkernels, left) at one order P."""
+        r, rp = self._arr(r)
+        M, Mp = self._arr(M)
+        assert M.size >= self.size(P)
+        out = np.zeros(self.size(P), self.dtype)
+        self._lib.or_m2l_single(P, rp, Mp, out.ctypes.data_as(self._P))
+        return out
+
+    def m2l_single_batch(self, P, r, C, nthreads=1):
+        r, rp = self._arr(np.reshape(r, (-1, 3)))
+        count = r.shape[0]
+        C, Cp = self._arr(np.reshape(C, (count, -1)))
+        out = np.zeros((count, self.size(P)), self.dtype)
+        self._lib.or_m2l_single_batch(count, P, rp, Cp, C.shape[1], out.ctypes.data_as(self._P), self.size(P),
+                                      nthreads)
+        return out
 
     def m2m(self, p_in, p_out, r, M):
         return self._tr(self._lib.or_m2m, p_in, p_out, r, M)

@@ -17,6 +17,8 @@
  *     sum_j q_j / |x - y_j| (addition theorem of the harmonics);
  *   - M2L: the double-height kernel of eq. (m2lkernels), right-hand form, summed over
  *     every k < p_in and every l = -k..k; mixed orders keep k < p_in, n < p_out;
+ *   - M2L, single-height kernel (eq. m2lkernels, left): the same sum truncated at
+ *     n + k <= P - 1;
  *   - M2M / L2L (the paper omits them, Section 1.2): the addition theorem
  *     R_n^m(a + b) = sum_{k,l} R_k^l(a) R_{n-k}^{m-l}(b) applied to the definitions:
  *       M'_n^m = sum_{k<=n, k<p_in} sum_l R_{n-k}^{m-l}(-r) M_k^l,
@@ -171,6 +173,35 @@ void or_m2l(int p_in, int p_out, const real *r, const real *M, real *L)
                     get(M, k, l, &mr, &mi);
                     get(S, n + k, m + l, &tr, &ti);
                     /* conj(M) * S */
+                    sr += mr * tr + mi * ti;
+                    si += mr * ti - mi * tr;
+                }
+            }
+            real sgn = (n % 2) ? -1 : 1;
+            L[pos(n, m)] = sgn * sr;
+            L[pos(n, m) + 1] = (m == 0) ? 0 : sgn * si;
+        }
+    }
+    free(S);
+}
+
+/*
+ * M2L, single-height kernel (eq. m2lkernels, left), one order P for input and output:
+ *   L_n^m = (-1)^n sum_{k=0}^{P-n-1} sum_{l=-k}^{k} conj(M_k^l) S_{n+k}^{m+l}(r),
+ * so only S up to degree P-1 is needed.
+ */
+void or_m2l_single(int P, const real *r, const real *M, real *L)
+{
+    real *S = (real *)malloc(sizeof(real) * (size_t)P * (P + 1));
+    or_singular(r, P, S);
+    for (int n = 0; n < P; ++n) {
+        for (int m = 0; m <= n; ++m) {
+            real sr = 0, si = 0;
+            for (int k = 0; k <= P - n - 1; ++k) {
+                for (int l = -k; l <= k; ++l) {
+                    real mr, mi, tr, ti;
+                    get(M, k, l, &mr, &mi);
+                    get(S, n + k, m + l, &tr, &ti);
                     sr += mr * tr + mi * ti;
                     si += mr * ti - mi * tr;
                 }
@@ -354,6 +385,15 @@ void or_translate_batch(int op, int64_t count, int p_in, int p_out, const real *
         else
             or_l2l(p_in, p_out, ri, src, dst);
     }
+}
+
+/* Single-height M2L over a batch (same layout as or_translate_batch, p_in = p_out = P). */
+void or_m2l_single_batch(int64_t count, int P, const real *r, const real *in, int64_t ld_in, real *out,
+                         int64_t ld_out, int nthreads)
+{
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < count; ++i)
+        or_m2l_single(P, r + 3 * i, in + i * ld_in, out + i * ld_out);
 }
 
 /* P2M of many clusters: cluster c has npts points at pts + 3*npts*c, charges q + npts*c. */

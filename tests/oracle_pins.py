@@ -217,6 +217,77 @@ def pin_m2l_vs_direct(o):
     return (0.0 if (decaying and ok_abs) else 1.0), 0.5
 
 
+def pin_m2l_single_zaxis(o):
+    """Single-height M2L (eq. m2lkernels, left) on the z axis: with S_j^i(0,0,R) =
+    delta_{i0} j!/R^{j+1}, L_n^m = (-1)^{n+m} sum_{k=m}^{P-1-n} (n+k)! M_k^m / R^{n+k+1}
+    (the z-axis form of eq. zm2lkernels with the single-height range of k)."""
+    rng = _rng(25)
+    err = 0.0
+    for (P, R) in ((1, 2.0), (2, 2.5), (6, 2.5), (9, 3.0)):
+        M = _random_solid(rng, P)
+        for sgn in (1.0, -1.0):
+            L = o.m2l_single(P, [0.0, 0.0, sgn * R], M)
+            ref = np.zeros(size(P))
+            for n in range(P):
+                for m in range(n + 1):
+                    for c in (0, 1):
+                        if c == 1 and m == 0:
+                            continue
+                        acc = 0.0
+                        for k in range(m, P - n):
+                            s = 1.0 if sgn > 0 else (-1.0) ** (n + k)
+                            acc += s * M[pos(k, m) + c] * math.factorial(n + k) / R ** (n + k + 1)
+                        ref[pos(n, m) + c] = (-1) ** (n + m) * acc
+            err = max(err, max_degree_error(L, ref, P, "L"))
+    return err, 1e-14
+
+
+def pin_m2l_single_vs_double_and_direct(o):
+    """Single height keeps the terms n + k <= P-1 of the double-height sum: row 0 equals the
+    double-height row 0, and a multipole with rows k < K only gives the double-height rows
+    n <= P-K.  Its expansion reproduces the direct potential with an error that decays in P
+    (eq. nbody), and a charge at the centre gives L_n^m = (-1)^n q S_n^m(r) (closed form);
+    the batch form equals the single calls."""
+    rng = _rng(26)
+    err = 0.0
+    pts, q = _cluster(rng, 20)
+    r = np.array([2.1, -1.3, 1.7])
+    for P in (5, 10):
+        M = o.p2m(P, [0, 0, 0], pts, q)
+        Ls, Ld = o.m2l_single(P, r, M), o.m2l(P, P, r, M)
+        err = max(err, _rel(Ls[: size(1)], Ld[: size(1)]))
+        K = 3
+        Mk = M.copy()
+        Mk[size(K):] = 0.0
+        Ls, Ld = o.m2l_single(P, r, Mk), o.m2l(P, P, r, Mk)
+        err = max(err, _rel(Ls[: size(P - K + 1)], Ld[: size(P - K + 1)]))
+    targets = r + rng.uniform(-0.5, 0.5, (6, 3))
+    exact = np.array([o.direct(pts, q, t) for t in targets])
+    errs = []
+    for P in (4, 8, 12, 16):
+        M = o.p2m(P, [0, 0, 0], pts, q)
+        L = o.m2l_single(P, r, M)
+        got = np.array([o.eval_l(P, r, L, t) for t in targets])
+        errs.append(np.max(np.abs(got - exact)) / np.max(np.abs(exact)))
+    if not (all(errs[i + 1] < errs[i] * 0.5 for i in range(3)) and errs[-1] < 1e-5):
+        err = max(err, 1.0)
+    P = 8
+    L = o.m2l_single(P, r, o.p2m(P, [0, 0, 0], [[0.0, 0.0, 0.0]], [0.7]))
+    ref = np.zeros(size(P))
+    Sc = singular_closed(r, P)
+    for n in range(P):
+        for m in range(n + 1):
+            ref[pos(n, m)] = (-1) ** n * 0.7 * Sc[pos(n, m)]
+            ref[pos(n, m) + 1] = (-1) ** n * 0.7 * Sc[pos(n, m) + 1] if m else 0.0
+    err = max(err, max_degree_error(L, ref, P, "L"))
+    rs = rng.normal(size=(3, 3)) * 2 + 3
+    Ms = np.stack([_random_solid(rng, 7) for _ in range(3)])
+    Lb = o.m2l_single_batch(7, rs, Ms, nthreads=2)
+    for i in range(3):
+        err = max(err, _rel(Lb[i], o.m2l_single(7, rs[i], Ms[i])))
+    return err, 1e-13
+
+
 def pin_m2l_mixed_orders(o):
     """The rows of a small p_out are the leading rows of a larger p_out (same p_in)."""
     rng = _rng(24)
@@ -440,6 +511,8 @@ PINS = [
     pin_m2l_zaxis_scaled,
     pin_m2l_vs_direct,
     pin_m2l_mixed_orders,
+    pin_m2l_single_zaxis,
+    pin_m2l_single_vs_double_and_direct,
     pin_m2m_exact,
     pin_m2m_composition,
     pin_m2m_mixed_orders,

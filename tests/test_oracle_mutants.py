@@ -32,6 +32,9 @@ MUTANTS = [
      "sr += ar * br - ai * bi;\n                    si += ai * br + ar * bi;", None),
     ("l2l_index", "int j = n - k, i = m - l;", "int j = n - k, i = l - m;", 1),
     ("eval_l_no_conj", "acc += ar * br + ai * bi;", "acc += ar * br - ai * bi;", 1),
+    ("m2l_single_range", "for (int k = 0; k <= P - n - 1; ++k) {", "for (int k = 0; k <= P - n; ++k) {", None),
+    ("m2l_single_low_order_S", "    real *S = (real *)malloc(sizeof(real) * (size_t)P * (P + 1));\n    or_singular(r, P, S);",
+     "    real *S = (real *)malloc(sizeof(real) * (size_t)P * (P + 1));\n    or_singular(r, P - 1, S);", None),
     ("l2p_dx_sign", "real xr = (ar - br) / 2, xi = (ai - bi) / 2;", "real xr = (br - ar) / 2, xi = (bi - ai) / 2;", None),
     ("l2p_dy_conj", "real yr = -(ai + bi) / 2, yi = (ar + br) / 2;", "real yr = (ai + bi) / 2, yi = -(ar + br) / 2;", None),
     ("l2p_dz_index", "get_r(R, n - 1, m, &cr, &ci);", "get_r(R, n - 1, m + 1, &cr, &ci);", None),
