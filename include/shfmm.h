@@ -68,6 +68,10 @@ typedef enum {
 enum { SH_M2M = 0, SH_M2L = 1, SH_L2L = 2 };  /* operations */
 enum { SH_F64 = 0, SH_F32 = 1 };              /* data types */
 #define SH_ACCUMULATE 1u /* add into the output instead of overwriting (Section 3.4 stores) */
+/* M2L by the single-height kernel (eq. m2lkernels, left): L_n^m keeps the terms with
+ * n + k <= P - 1 of the double-height sum (cheaper z-step, lower accuracy).  Accepted by
+ * the batched and indexed M2L calls with p_in = p_out = P; SH_EINVAL otherwise. */
+#define SH_SINGLE_HEIGHT 2u
 
 #define SH_MAX_ORDER 64
 
@@ -95,7 +99,8 @@ int sh_device_error(sh_ctx *ctx);
  * Translation i reads its shift at r[3i..3i+2], its input solid at in + i*ld_in
  * (p_in(p_in+1) reals) and writes out + i*ld_out (p_out(p_out+1) reals).
  * ld_in >= p_in(p_in+1), ld_out >= p_out(p_out+1).  count = 0 is a no-op.
- * flags: 0 or SH_ACCUMULATE (accumulate assumes the output solids do not overlap).
+ * flags: 0 or SH_ACCUMULATE (accumulate assumes the output solids do not overlap), and for
+ * M2L with p_in = p_out also SH_SINGLE_HEIGHT.
  * hip_stream: a hipStream_t, or NULL.
  * Errors: SH_EINVAL, SH_EORDER, SH_EDEVICE (launch failure).
  * Precision: FP64 results match the double-height sums of eq. (m2lkernels) to about

@@ -22,6 +22,7 @@ SH_OK, SH_EINVAL, SH_EORDER, SH_ESHIFT, SH_ENOMEM, SH_EDEVICE, SH_EBUSY = 0, -1,
 SH_M2M, SH_M2L, SH_L2L = 0, 1, 2
 SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
+SH_SINGLE_HEIGHT = 2  # single-height M2L (p_in = p_out)
 SH_PLAN_AUTOTUNE = 2
 SH_PLAN_NO_GRAPH = 4
 SH_SHARED_FP32 = 1

@@ -27,9 +27,11 @@ bool valid_dtype(int d) { return d == SH_F64 || d == SH_F32; }
 sh_status check_common(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
                        int64_t ld_in, int64_t ld_out, unsigned flags)
 {
-    if (!ctx || !valid_op(op) || !valid_dtype(dtype) || count < 0 || (flags & ~SH_ACCUMULATE))
+    if (!ctx || !valid_op(op) || !valid_dtype(dtype) || count < 0 || (flags & ~(SH_ACCUMULATE | SH_SINGLE_HEIGHT)))
         return SH_EINVAL;
     if (p_in < 1 || p_out < 1 || p_in > ctx->max_order || p_out > ctx->max_order) return SH_EORDER;
+    // the single-height kernel is defined for M2L with one order for input and output
+    if ((flags & SH_SINGLE_HEIGHT) && (op != SH_M2L || p_in != p_out)) return SH_EINVAL;
     if (ld_in < (int64_t)p_in * (p_in + 1) || ld_out < (int64_t)p_out * (p_out + 1)) return SH_EINVAL;
     return SH_OK;
 }
@@ -60,6 +62,7 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
     a.dst = dst;
     a.flags = flags;
     a.err = ctx->err_flag;
+    static_assert(SH_SINGLE_HEIGHT == shfmm::kSingleHeightFlag, "flag bit shared with the kernels");
     const bool f32 = dtype == SH_F32;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
@@ -70,7 +73,7 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
                               ld_out % 2 == 0 && ld_in < (1 << 24) && ld_out < (1 << 24);
     if (pair_aligned && shfmm::lpt_available(op, f32, p_in, p_out))
         e = shfmm::launch_lpt(ctx->tabs, a, f32, s);
-    else if (pair_aligned && shfmm::big_available(p_in, p_out))
+    else if (pair_aligned && !(flags & SH_SINGLE_HEIGHT) && shfmm::big_available(p_in, p_out))
         e = shfmm::launch_big(ctx->tabs, a, f32, s);
     else
         e = shfmm::launch_general(ctx->tabs, a, f32, s);
@@ -363,6 +366,7 @@ sh_status sh_m2l_naive_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t
                                  const double *in, int64_t ld_in, double *out, int64_t ld_out,
                                  unsigned flags, void *hip_stream)
 {
+    if (flags & SH_SINGLE_HEIGHT) return SH_EINVAL;  // the direct loop is the double-height sum
     sh_status st = check_common(ctx, SH_M2L, SH_F64, p_in, p_out, count, ld_in, ld_out, flags);
     if (st != SH_OK) return st;
     if (count == 0) return SH_OK;

@@ -72,7 +72,8 @@ __device__ __forceinline__ void zrot_rows(Real *x, const Real *er, const Real *e
 // Real: type of the solids and shifts in memory; Acc: arithmetic type (LDS state, tables).
 template <typename Real, typename Acc, int OP>
 __device__ void general_one(const DevTables &tab, int p_in, int p_out, double rx, double ry, double rz,
-                            const Real *in, Real *out, bool acc, int *err, unsigned char *smem_raw)
+                            const Real *in, Real *out, bool acc, int *err, unsigned char *smem_raw,
+                            bool single = false)
 {
     const int Pm = p_in > p_out ? p_in : p_out;
     const int S = Pm * (Pm + 1);
@@ -181,6 +182,8 @@ __device__ void general_one(const DevTables &tab, int p_in, int p_out, double rx
                 int lo = m, hi = p_in - 1;
                 if (OP == OP_M2M) hi = (o < hi) ? o : hi;
                 if (OP == OP_L2L) lo = o;
+                // single-height M2L (eq. m2lkernels, left): terms with o + i <= p_in - 1
+                if (OP == OP_M2L && single) hi = (p_in - 1 - o < hi) ? p_in - 1 - o : hi;
                 const Acc *zrow = Z + z_col_off(TP, m) + (int64_t)(o - m) * (TP - m) - m;
                 for (int i = lo; i <= hi; ++i) {
                     yr += zrow[i] * A[solid_pos(i, m)];
@@ -232,7 +235,8 @@ __global__ __launch_bounds__(64) void k_general(DevTables tab, TransArgs a)
         const int64_t di = a.dst ? a.dst[t] : t;
         general_one<Real, Acc, OP>(tab, a.p_in, a.p_out, (double)rr[3 * t], (double)rr[3 * t + 1],
                                    (double)rr[3 * t + 2], reinterpret_cast<const Real *>(a.in) + si * a.ld_in,
-                                   reinterpret_cast<Real *>(a.out) + di * a.ld_out, acc, a.err, smem_raw);
+                                   reinterpret_cast<Real *>(a.out) + di * a.ld_out, acc, a.err, smem_raw,
+                                   (a.flags & kSingleHeightFlag) != 0);
     }
 }
 

@@ -20,9 +20,10 @@ struct TransArgs {
     int64_t ld_out;
     const int64_t *src;  // optional gather indices
     const int64_t *dst;  // optional scatter indices
-    unsigned flags;      // bit 0: accumulate
+    unsigned flags;      // bit 0: accumulate; bit 1: single-height M2L (p_in = p_out)
     int *err;            // device error flag
 };
+constexpr unsigned kSingleHeightFlag = 2u;
 
 // One item of a mixed work list (same layout as the public sh_item): operation, orders,
 // input / output offsets (in reals) into the caller's arena, shift.

@@ -251,8 +251,11 @@ __device__ __forceinline__ void swap_row(cptr<Acc> T, const Acc (&xr)[N + 1], co
 // (M2M) of column 0 of the order-64 table holds it, and the few scalar-cache lines it spans
 // stay resident instead of one block of lines per column.  The normalised tables (FP32) are
 // read per column.  Entries outside the triangle of M2M / L2L are returned as 0 (unused).
+// single (M2L only): the single-height kernel (eq. m2lkernels, left) keeps the terms with
+// o + k <= PIN - 1; the others are returned as 0.  The coefficients are wave-uniform, so
+// the selection is a scalar operation and the double-height code runs unchanged.
 template <typename Real, typename Acc, int OP, int PIN, int M>
-__device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M])
+__device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M], bool single = false)
 {
     constexpr bool SEQ = std::is_same<Real, double>::value && std::is_same<Acc, double>::value;
     constexpr int K = kZTableOrder;
@@ -273,6 +276,7 @@ __device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M])
         } else {
             c[k - M] = Z[z_col_off(K, M) + (int64_t)(o - M) * (K - M) + (k - M)];
         }
+        if (OP == OP_M2L && o + k > PIN - 1) c[k - M] = single ? (Acc)0 : c[k - M];
     }
 }
 
@@ -446,6 +450,7 @@ void k_lpt(DevTables tab, TransArgs a)
     const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
     const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
+    const bool single = OP == OP_M2L && (a.flags & kSingleHeightFlag) != 0;
     const Real *__restrict__ rr = reinterpret_cast<const Real *>(a.r);
     const Real *__restrict__ gin = reinterpret_cast<const Real *>(a.in);
     Real *__restrict__ gout = reinterpret_cast<Real *>(a.out);
@@ -640,11 +645,11 @@ void k_lpt(DevTables tab, TransArgs a)
                 }
                 // coefficients of output o + 1 are fetched while output o is summed
                 Acc cz[PIN - m];
-                z_fetch<Real, Acc, OP, PIN, m>(Z, m, cz);
+                z_fetch<Real, Acc, OP, PIN, m>(Z, m, cz, single);
 #pragma unroll
                 for (int o = m; o < POUT; ++o) {
                     Acc nz[PIN - m];
-                    if (o + 1 < POUT) z_fetch<Real, Acc, OP, PIN, m>(Z, o + 1, nz);
+                    if (o + 1 < POUT) z_fetch<Real, Acc, OP, PIN, m>(Z, o + 1, nz, single);
                     Acc orr = 0, oi = 0;
 #pragma unroll
                     for (int k = m; k < PIN; ++k) {
