@@ -291,6 +291,27 @@ def run_l2p(sh, ctx, torch, dev, P=10, boxes=1 << 14, npts=64, reps=10):
             "bytes_per_target": 56}
 
 
+def run_fmm(sh, ctx, torch, dev, P=10, levels=4, npts=64, reps=3):
+    """One evaluation of the uniform-octree FMM (P2M, M2M, M2L, L2L, L2P, P2P) over 8^4 leaves
+    of 64 uniform particles each (262,144 particles, charges uniform in [-1, 1])."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    n = 2 ** levels
+    ijk = torch.stack(torch.meshgrid(*[torch.arange(n, device=dev, dtype=torch.float64)] * 3, indexing="ij"),
+                      -1).reshape(-1, 3)
+    pts = ((ijk[:, None, :] + torch.rand((n ** 3, npts, 3), generator=g, device=dev, dtype=torch.float64)) / n)
+    pts = pts.reshape(-1, 3).contiguous()
+    q = torch.rand((pts.shape[0],), generator=g, device=dev, dtype=torch.float64) * 2 - 1
+    out = torch.empty((pts.shape[0], 4), device=dev, dtype=torch.float64)
+    f = sh.Fmm(ctx, P, levels, (0.0, 0.0, 0.0), 1.0, npts)
+    s = time_launch(torch, lambda: f.evaluate(pts, q, out), reps)
+    d = f.describe()
+    f.close()
+    return {"particles": int(pts.shape[0]), "P": P, "levels": levels, "ms": round(s * 1e3, 3),
+            "particles_per_s": pts.shape[0] / s, "m2l_per_eval": d["m2l"], "m2m_per_eval": d["m2m"],
+            "l2l_per_eval": d["l2l"], "translation_calls": d["calls"]}
+
+
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
     (the stream the library launches on by default)."""
@@ -483,6 +504,9 @@ def main():
             log(f"[bench] mixed-order list {name}")
             extra[f"mixed_list_{name}"] = run_mixed(sh, ctx, torch, dev, dt)
             torch.cuda.empty_cache()
+        log("[bench] FMM P=10 262144 particles")
+        extra["fmm_p10_uniform_262k"] = run_fmm(sh, ctx, torch, dev)
+        torch.cuda.empty_cache()
         log("[bench] L2P P=10")
         extra["l2p_p10_f64"] = run_l2p(sh, ctx, torch, dev)
         torch.cuda.empty_cache()

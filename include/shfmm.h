@@ -369,6 +369,37 @@ sh_status sh_l2p_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double
                            int64_t npts, const double *pts, const double *L, int64_t ldL,
                            double *out, unsigned flags, void *hip_stream);
 
+/* ---------------- uniform-octree FMM driver ----------------
+ * The translations used inside a fast multipole method, as the paper intends (Sections 1
+ * and 2): P2M at the leaves, upward M2M, M2L over the interaction lists (boxes whose parents
+ * are neighbours but which are not neighbours themselves), downward L2L, L2P at the leaves
+ * and the direct near field (P2P) over the 27 neighbouring leaves, for the potential
+ * u(x_i) = sum_{j != i} q_j / |x_i - x_j| (eq. nbody) and its gradient.
+ * The tree is a full octree with `levels` levels below the root cube [origin, origin+width)^3:
+ * leaf (ix, iy, iz) of the n = 2^levels per side has index (ix n + iy) n + iz and holds
+ * exactly `npts` particles, stored leaf by leaf (particle j of leaf b at pts[3(npts b + j)]).
+ * Particles must lie in their leaf's cube (the expansions converge only then).  FP64.
+ * Every index and shift array is built and uploaded at creation; the handle owns its device
+ * memory (multipole and local pools of every level, the call lists).  Handles are not
+ * thread-safe: one evaluation at a time per handle. */
+#define SH_FMM_MAX_LEVELS 6
+typedef struct sh_fmm sh_fmm;
+
+/* levels in [2, SH_FMM_MAX_LEVELS], npts >= 1, width > 0, 1 <= P <= the context's order.
+ * Errors: SH_EINVAL, SH_EORDER, SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], double width,
+                        int64_t npts, sh_fmm **out);
+void sh_fmm_destroy(sh_fmm *fmm);
+
+/* One evaluation on device pointers, stream-ordered: pts (N x 3, leaf by leaf), charges q
+ * (N), out (N x 4) receives {u, du/dx, du/dy, du/dz} at every particle (the field is minus
+ * the gradient).  N = 8^levels * npts.  Errors: SH_EINVAL, SH_EDEVICE. */
+sh_status sh_fmm_evaluate(sh_fmm *fmm, const double *pts, const double *q, double *out,
+                          void *hip_stream);
+
+/* counts[0..4] = M2M, M2L and L2L translations per evaluation, translation calls, leaves. */
+sh_status sh_fmm_describe(const sh_fmm *fmm, int64_t *counts);
+
 /* ---------------- host-only helpers (no device needed) ----------------
  * Dense (n+1)x(n+1) row-major swap matrix of degree n (0 <= n < SH_MAX_ORDER), rounded
  * once from exact arithmetic.  which: 0 = F (M side, real parts), 1 = G (M side,

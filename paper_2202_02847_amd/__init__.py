@@ -57,6 +57,10 @@ _SIGS = {
     "sh_m2l_naive_batch_f64": (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
     "sh_p2m_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _vp, _c_i64, _vp]),
     "sh_l2p_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_u32, _vp]),
+    "sh_fmm_create": (_c_i32, [_vp, _c_i32, _c_i32, _vp, ctypes.c_double, _c_i64, _vp]),
+    "sh_fmm_destroy": (None, [_vp]),
+    "sh_fmm_evaluate": (_c_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "sh_fmm_describe": (_c_i32, [_vp, _vp]),
     "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
     "sh_normalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
     "sh_denormalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
@@ -550,3 +554,55 @@ def sh_server_drain(server: Server) -> None:
 
 def sh_server_stats_get(server: Server) -> dict:
     return server.stats()
+
+
+def sh_fmm_create(ctx, P, levels, origin, width, npts):
+    """Returns the sh_fmm handle (a ctypes.c_void_p)."""
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    h = ctypes.c_void_p()
+    _check(lib().sh_fmm_create(_h(ctx), int(P), int(levels), o, float(width), int(npts), ctypes.byref(h)),
+           "sh_fmm_create")
+    return h
+
+
+def sh_fmm_destroy(h):
+    lib().sh_fmm_destroy(h)
+
+
+def sh_fmm_evaluate(h, pts, q, out, stream=None):
+    _check(lib().sh_fmm_evaluate(h, _ptr(pts), _ptr(q), _ptr(out), _stream(stream)), "sh_fmm_evaluate")
+
+
+def sh_fmm_describe(h):
+    """[M2M, M2L, L2L translations per evaluation, translation calls, leaves]."""
+    c = (ctypes.c_int64 * 5)()
+    _check(lib().sh_fmm_describe(h, c), "sh_fmm_describe")
+    return list(c)
+
+
+class Fmm:
+    """Uniform-octree FMM handle (sh_fmm_*): P2M, M2M, M2L, L2L, L2P and P2P on the device."""
+
+    def __init__(self, ctx, P, levels, origin, width, npts):
+        self._ctx = ctx
+        self._h = sh_fmm_create(ctx, P, levels, origin, width, npts)
+        self.P, self.levels, self.npts = int(P), int(levels), int(npts)
+        self.n_particles = 8 ** self.levels * self.npts
+
+    def evaluate(self, pts, q, out, stream=None):
+        sh_fmm_evaluate(self._h, pts, q, out, stream)
+
+    def describe(self):
+        c = sh_fmm_describe(self._h)
+        return {"m2m": c[0], "m2l": c[1], "l2l": c[2], "calls": c[3], "leaves": c[4]}
+
+    def close(self):
+        if self._h:
+            sh_fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

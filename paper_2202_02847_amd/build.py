@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libshfmm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "plan.cpp", "server.cpp", "shared.cpp", "tables.cpp", "k_general.hip", "k_aux.hip", "k_lpt.hip",
+SOURCES = ["api.cpp", "plan.cpp", "server.cpp", "shared.cpp", "tables.cpp", "fmm.cpp", "k_general.hip", "k_aux.hip", "k_lpt.hip",
            "k_shared.hip", "k_big.hip"] + [
     f"k_{kind}_{dt}_{op}.hip" for kind in ("lpt", "list") for dt in ("f64", "f32") for op in ("m2m", "m2l", "l2l")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -4,8 +4,10 @@
 //   * P2M (eq. MLexpansions: M_n^m = sum_j q_j R_n^m(y_j - x_A)), R by the Appendix
 //     recurrences, used to build multipole inputs on the device;
 //   * L2P: the potential of a local expansion (eq. MLexpansions) and its gradient at
-//     target points.
+//     target points;
+//   * P2P: the direct near-field sum over neighbouring boxes (eq. nbody).
 #include "kernels.hpp"
+#include "near_field.hpp"
 
 namespace shfmm {
 
@@ -249,6 +251,57 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
     }
 }
 
+// P2P (the near field of eq. nbody with G = 1/|x - y|): one lane per target, the 64 lanes of a
+// wavefront on targets of one box; the sources of each neighbour box (nbr[27c + k], -1 for
+// none) are read by wave-uniform scalar loads.  Adds q_j / |x - y_j| and its gradient
+// -q_j (x - y_j) / |x - y_j|^3 over sources at a distance > 0 (a target does not see itself).
+__global__ __launch_bounds__(256) void k_p2p(int64_t count, int64_t chunks, int64_t npts, const double *pts,
+                                             const double *q, const int32_t *nbr, double *out, unsigned flags)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t ntask = count * chunks;
+    const bool acc = (flags & 1u) != 0;
+    const lpt_cptr P = (lpt_cptr)pts;
+    const lpt_cptr Q = (lpt_cptr)q;
+    const __attribute__((address_space(4))) int32_t *NB = (const __attribute__((address_space(4))) int32_t *)nbr;
+    for (int64_t task = (int64_t)blockIdx.x * 4 + wave; task < ntask; task += (int64_t)gridDim.x * 4) {
+        const int64_t c = task / chunks;
+        const int64_t j0 = (task - c * chunks) * 64 + lane;
+        const bool act = j0 < npts;
+        const int64_t t = c * npts + (act ? j0 : 0);
+        const double x = pts[3 * t], y = pts[3 * t + 1], z = pts[3 * t + 2];
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int k = 0; k < 27; ++k) {
+            const int32_t b = NB[27 * c + k];
+            if (b < 0) continue;
+            const int64_t s0 = (int64_t)b * npts;
+            for (int64_t s = 0; s < npts; ++s) {
+                const double dx = x - P[3 * (s0 + s)], dy = y - P[3 * (s0 + s) + 1], dz = z - P[3 * (s0 + s) + 2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double inv = (r2 > 0.0) ? 1.0 / sqrt(r2) : 0.0;
+                const double qi = Q[s0 + s] * inv;
+                const double qi3 = qi * inv * inv;
+                phi += qi;
+                gx -= qi3 * dx;
+                gy -= qi3 * dy;
+                gz -= qi3 * dz;
+            }
+        }
+        if (act) {
+            double *o = out + 4 * t;
+            if (acc) {
+                phi += o[0];
+                gx += o[1];
+                gy += o[2];
+                gz += o[3];
+            }
+            *reinterpret_cast<double2 *>(o) = double2{phi, gx};
+            *reinterpret_cast<double2 *>(o + 2) = double2{gy, gz};
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_m2l_naive(const TransArgs &a, hipStream_t s)
@@ -280,6 +333,17 @@ hipError_t launch_l2p(int P, int64_t count, const double *centres, int64_t npts,
     const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
     hipLaunchKernelGGL(k_l2p, dim3((unsigned)grid64), dim3(256), 0, s, P, count, chunks, centres, npts, pts, L, ldL,
                        out, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(int64_t count, int64_t npts, const double *pts, const double *q, const int32_t *nbr,
+                      double *out, unsigned flags, hipStream_t s)
+{
+    if (count <= 0 || npts <= 0) return hipSuccess;
+    const int64_t chunks = (npts + 63) / 64;
+    const int64_t blocks = (count * chunks + 3) / 4;
+    const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
+    hipLaunchKernelGGL(k_p2p, dim3((unsigned)grid64), dim3(256), 0, s, count, chunks, npts, pts, q, nbr, out, flags);
     return hipGetLastError();
 }
 

@@ -1,0 +1,178 @@
+"""The uniform-octree FMM driver (sh_fmm_*) against the same FMM composed from oracle
+primitives on the CPU, and against the direct sum (eq. nbody).
+
+The CPU composition below builds its own box numbering, interaction lists and neighbour
+lists with numpy (it shares nothing with the library's driver) and runs the oracle's P2M,
+M2M, double-height M2L, L2L and L2P with the direct near field; the GPU result must match it
+to 1e-11 of the largest value (the two differ only by rounding).  Against the direct sum the
+error is the method's truncation error, which must fall with the order.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2202_02847_amd as sh
+from gpu_util import torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sh.Context(max_order=32, device=0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+def _grid(level):
+    n = 2 ** level
+    ijk = np.array(list(itertools.product(range(n), repeat=3)), dtype=np.int64)  # index (i n + j) n + k
+    return n, ijk
+
+
+def _centres(level, origin, width):
+    n, ijk = _grid(level)
+    return np.asarray(origin, float) + (ijk + 0.5) * (width / n)
+
+
+def _particles(levels, npts, origin, width, seed):
+    """npts uniform particles in every leaf, stored leaf by leaf; charges uniform in [-1, 1]."""
+    rng = np.random.default_rng(seed)
+    n, ijk = _grid(levels)
+    w = width / n
+    lo = np.asarray(origin, float) + ijk * w
+    pts = lo[:, None, :] + rng.uniform(0.0, w, (len(ijk), npts, 3))
+    q = rng.uniform(-1.0, 1.0, (len(ijk), npts))
+    return pts, q
+
+
+def _direct(pts, q, targets=None):
+    """u(x_i) = sum_{j != i} q_j / |x_i - x_j| and its gradient (eq. nbody)."""
+    x = pts.reshape(-1, 3)
+    qq = q.reshape(-1)
+    idx = np.arange(len(x)) if targets is None else targets
+    out = np.zeros((len(idx), 4))
+    for a in range(0, len(idx), 256):
+        ii = idx[a: a + 256]
+        d = x[ii][:, None, :] - x[None, :, :]
+        r = np.sqrt(np.sum(d * d, axis=2))
+        r[np.arange(len(ii)), ii] = np.inf
+        inv = 1.0 / r
+        out[a: a + 256, 0] = inv @ qq
+        out[a: a + 256, 1:] = -np.einsum("ij,ijk->ik", (inv ** 3) * qq[None, :], d)
+    return out
+
+
+def _oracle_fmm(orc, P, levels, origin, width, pts, q):
+    """The FMM from oracle primitives: P2M, M2M up, M2L over interaction lists, L2L down, L2P,
+    plus the direct near field over the 27 neighbouring leaves."""
+    nleaf, npts = q.shape
+    th = 16
+    M = {levels: orc.p2m_batch(P, _centres(levels, origin, width), pts, q, nthreads=th)}
+    for lev in range(levels, 0, -1):
+        n, ijk = _grid(lev)
+        parent = ((ijk[:, 0] // 2) * (n // 2) + ijk[:, 1] // 2) * (n // 2) + ijk[:, 2] // 2
+        r = _centres(lev - 1, origin, width)[parent] - _centres(lev, origin, width)
+        moved = orc.translate_batch("m2m", P, P, r, M[lev], nthreads=th)
+        M[lev - 1] = np.zeros((8 ** (lev - 1), moved.shape[1]))
+        np.add.at(M[lev - 1], parent, moved)
+    Lx = {}
+    for lev in range(2, levels + 1):
+        n, ijk = _grid(lev)
+        c = _centres(lev, origin, width)
+        src, dst = [], []
+        for b, (i, j, k) in enumerate(ijk):
+            for s, (a, bb, cc) in enumerate(ijk):
+                if max(abs(a - i), abs(bb - j), abs(cc - k)) < 2:
+                    continue  # neighbours (near field or parent level)
+                if max(abs(a // 2 - i // 2), abs(bb // 2 - j // 2), abs(cc // 2 - k // 2)) > 1:
+                    continue  # handled at the parent level
+                src.append(s)
+                dst.append(b)
+        src, dst = np.array(src), np.array(dst)
+        out = orc.translate_batch("m2l", P, P, c[dst] - c[src], M[lev][src], nthreads=th)
+        Lx[lev] = np.zeros((8 ** lev, out.shape[1]))
+        np.add.at(Lx[lev], dst, out)
+    for lev in range(2, levels):
+        n, ijk = _grid(lev + 1)
+        parent = ((ijk[:, 0] // 2) * (n // 2) + ijk[:, 1] // 2) * (n // 2) + ijk[:, 2] // 2
+        r = _centres(lev + 1, origin, width) - _centres(lev, origin, width)[parent]
+        Lx[lev + 1] += orc.translate_batch("l2l", P, P, r, Lx[lev][parent], nthreads=th)
+    far = orc.l2p_batch(P, _centres(levels, origin, width), pts, Lx[levels], nthreads=th)
+    n, ijk = _grid(levels)
+    near = np.zeros_like(far)
+    for b, (i, j, k) in enumerate(ijk):
+        nb = [s for s, (a, bb, cc) in enumerate(ijk) if max(abs(a - i), abs(bb - j), abs(cc - k)) <= 1]
+        ys = pts[nb].reshape(-1, 3)
+        qs = q[nb].reshape(-1)
+        d = pts[b][:, None, :] - ys[None, :, :]
+        r = np.sqrt(np.sum(d * d, axis=2))
+        inv = np.where(r > 0, 1.0 / np.where(r > 0, r, 1.0), 0.0)
+        near[b, :, 0] = inv @ qs
+        near[b, :, 1:] = -np.einsum("ij,ijk->ik", (inv ** 3) * qs[None, :], d)
+    return (far + near).reshape(-1, 4)
+
+
+def _gpu_fmm(ctx, P, levels, origin, width, pts, q):
+    torch, dev = torch_dev()
+    f = sh.Fmm(ctx, P, levels, origin, width, q.shape[1])
+    d_p = torch.from_numpy(np.ascontiguousarray(pts.reshape(-1, 3))).to(dev)
+    d_q = torch.from_numpy(np.ascontiguousarray(q.reshape(-1))).to(dev)
+    d_o = torch.full((q.size, 4), np.nan, dtype=torch.float64, device=dev)
+    f.evaluate(d_p, d_q, d_o)
+    torch.cuda.synchronize()
+    desc = f.describe()
+    f.close()
+    return d_o.cpu().numpy(), desc
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("P,levels,npts", [(6, 2, 5), (10, 3, 9), (17, 3, 3)])
+def test_fmm_matches_oracle_composition(ctx, orc, P, levels, npts):
+    origin, width = (-0.3, 0.1, 0.25), 2.0
+    print(f"[fmm] P={P} levels={levels} npts={npts}", flush=True)
+    pts, q = _particles(levels, npts, origin, width, seed=P * 10 + levels)
+    got, desc = _gpu_fmm(ctx, P, levels, origin, width, pts, q)
+    assert np.isfinite(got).all()
+    ref = _oracle_fmm(orc, P, levels, origin, width, pts, q)
+    assert _rel(got[:, 0], ref[:, 0]) <= 1e-11
+    assert _rel(got[:, 1:], ref[:, 1:]) <= 1e-11
+    assert desc["leaves"] == 8 ** levels
+
+
+def test_fmm_truncation_error_falls_with_order(ctx):
+    """Against the direct sum: the error of the potential and gradient falls with P."""
+    levels, npts = 3, 16
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=5)
+    exact = _direct(pts, q)
+    errs = []
+    for P in (4, 8, 12, 16):
+        got, _ = _gpu_fmm(ctx, P, levels, origin, width, pts, q)
+        errs.append((_rel(got[:, 0], exact[:, 0]), _rel(got[:, 1:], exact[:, 1:])))
+    print("[fmm] errors vs direct", errs, flush=True)
+    for a, b in zip(errs, errs[1:]):
+        assert b[0] < a[0] and b[1] < a[1]
+    # the CPU composition of the same method gives 2.5e-7 and 8.4e-8 at P = 16
+    assert errs[-1][0] < 1e-5 and errs[-1][1] < 1e-5
+
+
+def test_fmm_rejects_bad_arguments(ctx):
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 10, 1, (0, 0, 0), 1.0, 8)  # fewer than two levels: no interaction list
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 10, 7, (0, 0, 0), 1.0, 8)  # above SH_FMM_MAX_LEVELS
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 10, 3, (0, 0, 0), 0.0, 8)  # empty cube
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 33, 3, (0, 0, 0), 1.0, 8)  # order above the context's
