@@ -23,6 +23,7 @@ SH_M2M, SH_M2L, SH_L2L = 0, 1, 2
 SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
 SH_SINGLE_HEIGHT = 2  # single-height M2L (p_in = p_out)
+SH_FMM_NO_GRAPH = 1
 SH_PLAN_AUTOTUNE = 2
 SH_PLAN_NO_GRAPH = 4
 SH_SHARED_FP32 = 1
@@ -59,7 +60,7 @@ _SIGS = {
     "sh_l2p_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_u32, _vp]),
     "sh_fmm_create": (_c_i32, [_vp, _c_i32, _c_i32, _vp, ctypes.c_double, _c_i64, _vp]),
     "sh_fmm_destroy": (None, [_vp]),
-    "sh_fmm_evaluate": (_c_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "sh_fmm_evaluate": (_c_i32, [_vp, _vp, _vp, _vp, _c_u32, _vp]),
     "sh_fmm_describe": (_c_i32, [_vp, _vp]),
     "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
     "sh_normalise_f64": (_c_i32, [_c_i32, _c_i32, _c_i64, _vp, _c_i64]),
@@ -569,8 +570,8 @@ def sh_fmm_destroy(h):
     lib().sh_fmm_destroy(h)
 
 
-def sh_fmm_evaluate(h, pts, q, out, stream=None):
-    _check(lib().sh_fmm_evaluate(h, _ptr(pts), _ptr(q), _ptr(out), _stream(stream)), "sh_fmm_evaluate")
+def sh_fmm_evaluate(h, pts, q, out, flags=0, stream=None):
+    _check(lib().sh_fmm_evaluate(h, _ptr(pts), _ptr(q), _ptr(out), flags, _stream(stream)), "sh_fmm_evaluate")
 
 
 def sh_fmm_describe(h):
@@ -589,8 +590,8 @@ class Fmm:
         self.P, self.levels, self.npts = int(P), int(levels), int(npts)
         self.n_particles = 8 ** self.levels * self.npts
 
-    def evaluate(self, pts, q, out, stream=None):
-        sh_fmm_evaluate(self._h, pts, q, out, stream)
+    def evaluate(self, pts, q, out, flags=0, stream=None):
+        sh_fmm_evaluate(self._h, pts, q, out, flags, stream)
 
     def describe(self):
         c = sh_fmm_describe(self._h)

@@ -13,12 +13,17 @@
 //     the first overwrites the parents, the other seven accumulate.
 //   * M2L at level l >= 2: one call per offset d in [-3, 3]^3 \ [-1, 1]^3 (316 offsets); the
 //     pairs (b + d -> b) of an offset have distinct targets b.  The pair is in the interaction
-//     list of b when the parents of b and b + d are neighbours (or equal).
+//     list of b when the parents of b and b + d are neighbours (or equal).  A level's calls
+//     are split into kGroups groups of about equal work; group g accumulates into its own
+//     partial pool, so the groups run concurrently (graph branches), and one kernel adds the
+//     partial pools into the local expansions.
 //   * L2L, level l -> l+1: one call per child octant, accumulating into the children.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -34,7 +39,10 @@ struct FmmCall {
     int level_in, level_out;
     int64_t count;
     int64_t off;  // first pair in the shared src / dst / r arrays
+    int group;    // M2L: partial pool the call accumulates into
 };
+
+constexpr int kGroups = 8;
 
 }  // namespace
 
@@ -50,11 +58,20 @@ struct sh_fmm {
     // device memory: one allocation
     void *mem = nullptr;
     double *M = nullptr, *L = nullptr;  // pools: nbox solids of P(P+1) reals
+    double *part = nullptr;             // kGroups partial pools of levels 2..L
     int64_t *src = nullptr, *dst = nullptr;
     double *r = nullptr;
     double *leaf_centres = nullptr;
     int32_t *nbr = nullptr;  // leaves x 27
     int64_t npairs = 0;
+    // graph replay: captured on `cap` with branches on `side`, for one (pts, q, out)
+    std::mutex mu;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
+    hipGraphExec_t exec = nullptr;
+    const double *g_pts = nullptr, *g_q = nullptr;
+    double *g_out = nullptr;
 };
 
 namespace {
@@ -88,7 +105,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
         const double w = f->width / (double)n;
         for (int o = 0; o < 8; ++o) {
             const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_M2M, l, l - 1, 0, (int64_t)hp.src.size()};
+            FmmCall c{SH_M2M, l, l - 1, 0, (int64_t)hp.src.size(), 0};
             for (int64_t px = 0; px < np; ++px)
                 for (int64_t py = 0; py < np; ++py)
                     for (int64_t pz = 0; pz < np; ++pz)
@@ -106,7 +123,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
             for (int dy = -3; dy <= 3; ++dy)
                 for (int dz = -3; dz <= 3; ++dz) {
                     if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-                    FmmCall c{SH_M2L, l, l, 0, (int64_t)hp.src.size()};
+                    FmmCall c{SH_M2L, l, l, 0, (int64_t)hp.src.size(), 0};
                     for (int64_t ix = 0; ix < n; ++ix) {
                         const int64_t sx = ix + dx;
                         if (sx < 0 || sx >= n) continue;
@@ -130,6 +147,20 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
                     c.count = (int64_t)hp.src.size() - c.off;
                     if (c.count > 0) f->m2l.push_back(c);
                 }
+        // groups of about equal work: each call to the least loaded group, largest first
+        std::vector<size_t> idx;
+        for (size_t i = 0; i < f->m2l.size(); ++i)
+            if (f->m2l[i].level_in == l) idx.push_back(i);
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](size_t a, size_t b) { return f->m2l[a].count > f->m2l[b].count; });
+        int64_t load[kGroups] = {0};
+        for (size_t i : idx) {
+            int g = 0;
+            for (int k = 1; k < kGroups; ++k)
+                if (load[k] < load[g]) g = k;
+            f->m2l[i].group = g;
+            load[g] += f->m2l[i].count;
+        }
     }
     // downward: parents at level l -> children at level l + 1 (octant o), from level 2
     for (int l = 2; l < Lv; ++l) {
@@ -137,7 +168,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
         const double w = f->width / (double)n;
         for (int o = 0; o < 8; ++o) {
             const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size()};
+            FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size(), 0};
             for (int64_t px = 0; px < np; ++px)
                 for (int64_t py = 0; py < np; ++py)
                     for (int64_t pz = 0; pz < np; ++pz)
@@ -217,7 +248,9 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
         delete f;
         return SH_EDEVICE;
     }
-    if (hipMalloc(&f->mem, 2 * bM + 2 * bI + bR + bC + bN) != hipSuccess) {
+    const int64_t part_reals = (f->nbox - f->lvl_off[2]) * S;  // levels 2..L
+    const size_t bP = up256(sizeof(double) * (size_t)(kGroups * part_reals));
+    if (hipMalloc(&f->mem, 2 * bM + 2 * bI + bR + bC + bN + bP) != hipSuccess) {
         (void)hipGetLastError();
         delete f;
         return SH_ENOMEM;
@@ -230,6 +263,7 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
     f->r = reinterpret_cast<double *>(p + 2 * bM + 2 * bI);
     f->leaf_centres = reinterpret_cast<double *>(p + 2 * bM + 2 * bI + bR);
     f->nbr = reinterpret_cast<int32_t *>(p + 2 * bM + 2 * bI + bR + bC);
+    f->part = reinterpret_cast<double *>(p + 2 * bM + 2 * bI + bR + bC + bN);
     bool ok = hipMemcpy(f->src, hp.src.data(), sizeof(int64_t) * hp.src.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(f->dst, hp.dst.data(), sizeof(int64_t) * hp.dst.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(f->r, hp.r.data(), sizeof(double) * hp.r.size(), hipMemcpyHostToDevice) == hipSuccess &&
@@ -250,49 +284,139 @@ void sh_fmm_destroy(sh_fmm *f)
     if (!f) return;
     {
         DeviceGuard g(f->ctx->device);
+        if (f->exec) (void)hipGraphExecDestroy(f->exec);
+        for (hipEvent_t e : f->ev) (void)hipEventDestroy(e);
+        for (hipStream_t st : f->side) (void)hipStreamDestroy(st);
+        if (f->cap) (void)hipStreamDestroy(f->cap);
         if (f->mem) (void)hipFree(f->mem);
     }
     delete f;
 }
 
-sh_status sh_fmm_evaluate(sh_fmm *f, const double *pts, const double *q, double *out, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+hipError_t status_to_hip(sh_status st) { return st == SH_OK ? hipSuccess : hipErrorUnknown; }
+
+// Enqueues one evaluation on stream s.  With fork (graph capture), the near field runs on
+// side[0] from the start and M2L group g on side[1 + g]: the near field writes the output
+// first (overwrite) while the far field is computed, and L2P adds the far field last.  The
+// calls of one group stay in order (their targets overlap across offsets).
+hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, hipStream_t s, bool fork)
 {
-    if (!f || !pts || !q || !out) return SH_EINVAL;
-    DeviceGuard g(f->ctx->device);
-    if (!g.ok) return SH_EDEVICE;
-    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int P = f->P, Lv = f->levels;
     const int64_t S = (int64_t)P * (P + 1);
     const int64_t nleaf = boxes_at(Lv);
     double *Mleaf = f->M + f->lvl_off[Lv] * S;
     double *Lleaf = f->L + f->lvl_off[Lv] * S;
-    if (shfmm::launch_p2m(P, nleaf, f->leaf_centres, f->npts, pts, q, Mleaf, S, s) != hipSuccess) return SH_EDEVICE;
-    auto run = [&](const FmmCall &c, double *pool_in, double *pool_out, unsigned flags) {
-        return shfmm::translate_device(f->ctx, c.op, SH_F64, P, P, c.count, f->r + 3 * c.off, f->src + c.off,
-                                       pool_in + f->lvl_off[c.level_in] * S, S, f->dst + c.off,
-                                       pool_out + f->lvl_off[c.level_out] * S, S, flags, hip_stream);
+    double *L2 = f->L + f->lvl_off[2] * S;  // levels 2..L
+    const int64_t part_reals = (f->nbox - f->lvl_off[2]) * S;
+    hipError_t e;
+    hipStream_t near = s;
+    if (fork) {
+        if ((e = hipEventRecord(f->ev[0], s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(f->side[0], f->ev[0], 0)) != hipSuccess) return e;
+        near = f->side[0];
+    }
+    if ((e = shfmm::launch_p2p(nleaf, f->npts, pts, q, f->nbr, out, 0u, near)) != hipSuccess) return e;
+    if ((e = shfmm::launch_p2m(P, nleaf, f->leaf_centres, f->npts, pts, q, Mleaf, S, s)) != hipSuccess) return e;
+    // pool_out + (level_out's first box - out_first) solids: the output level's solids
+    auto run = [&](const FmmCall &c, const double *pool_in, double *pool_out, int64_t out_first, unsigned flags,
+                   hipStream_t st) {
+        return status_to_hip(shfmm::translate_device(f->ctx, c.op, SH_F64, P, P, c.count, f->r + 3 * c.off,
+                                                     f->src + c.off, pool_in + f->lvl_off[c.level_in] * S, S,
+                                                     f->dst + c.off,
+                                                     pool_out + (f->lvl_off[c.level_out] - out_first) * S, S, flags,
+                                                     st));
     };
     // upward pass: the first octant of a level overwrites its parents
-    for (size_t i = 0; i < f->up.size(); ++i) {
-        const sh_status st = run(f->up[i], f->M, f->M, (i % 8 == 0) ? 0u : SH_ACCUMULATE);
-        if (st != SH_OK) return st;
+    for (size_t i = 0; i < f->up.size(); ++i)
+        if ((e = run(f->up[i], f->M, f->M, 0, (i % 8 == 0) ? 0u : SH_ACCUMULATE, s)) != hipSuccess) return e;
+    // local expansions and the partial pools start at zero at levels 2..L
+    if ((e = shfmm::launch_zero(L2, part_reals, s)) != hipSuccess) return e;
+    if ((e = shfmm::launch_zero(f->part, kGroups * part_reals, s)) != hipSuccess) return e;
+    if (fork) {
+        if ((e = hipEventRecord(f->ev[1], s)) != hipSuccess) return e;
+        for (int g = 0; g < kGroups; ++g)
+            if ((e = hipStreamWaitEvent(f->side[1 + g], f->ev[1], 0)) != hipSuccess) return e;
     }
-    // local expansions start at zero at levels 2..L (levels 0 and 1 have no interaction list)
-    if (hipMemsetAsync(f->L + f->lvl_off[2] * S, 0, sizeof(double) * (size_t)((f->nbox - f->lvl_off[2]) * S), s) !=
-        hipSuccess)
-        return SH_EDEVICE;
+    // the partial pool of group g stands in for the L pool of levels 2..L
     for (const FmmCall &c : f->m2l) {
-        const sh_status st = run(c, f->M, f->L, SH_ACCUMULATE);
-        if (st != SH_OK) return st;
+        double *pool = f->part + c.group * part_reals;
+        if ((e = run(c, f->M, pool, f->lvl_off[2], SH_ACCUMULATE, fork ? f->side[1 + c.group] : s)) != hipSuccess)
+            return e;
     }
-    for (const FmmCall &c : f->down) {
-        const sh_status st = run(c, f->L, f->L, SH_ACCUMULATE);
-        if (st != SH_OK) return st;
+    if (fork) {
+        for (int g = 0; g < kGroups; ++g) {
+            if ((e = hipEventRecord(f->ev[2 + g], f->side[1 + g])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, f->ev[2 + g], 0)) != hipSuccess) return e;
+        }
     }
-    if (shfmm::launch_l2p(P, nleaf, f->leaf_centres, f->npts, pts, Lleaf, S, out, 0u, s) != hipSuccess)
-        return SH_EDEVICE;
-    if (shfmm::launch_p2p(nleaf, f->npts, pts, q, f->nbr, out, 1u, s) != hipSuccess) return SH_EDEVICE;
-    return SH_OK;
+    if ((e = shfmm::launch_add_parts(L2, f->part, kGroups, part_reals, part_reals, s)) != hipSuccess) return e;
+    for (const FmmCall &c : f->down)
+        if ((e = run(c, f->L, f->L, 0, SH_ACCUMULATE, s)) != hipSuccess) return e;
+    if (fork) {
+        if ((e = hipEventRecord(f->ev[2 + kGroups], f->side[0])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, f->ev[2 + kGroups], 0)) != hipSuccess) return e;
+    }
+    return shfmm::launch_l2p(P, nleaf, f->leaf_centres, f->npts, pts, Lleaf, S, out, 1u, s);
+}
+
+hipError_t capture(sh_fmm *f, const double *pts, const double *q, double *out)
+{
+    hipError_t e;
+    if (f->exec) {
+        (void)hipGraphExecDestroy(f->exec);
+        f->exec = nullptr;
+    }
+    if (!f->cap) {
+        if ((e = hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking)) != hipSuccess) return e;
+        for (int i = 0; i < 1 + kGroups; ++i) {
+            hipStream_t st;
+            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+            f->side.push_back(st);
+        }
+        for (int i = 0; i < 3 + kGroups; ++i) {
+            hipEvent_t ev;
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+            f->ev.push_back(ev);
+        }
+    }
+    if ((e = hipStreamBeginCapture(f->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+    const hipError_t le = enqueue(f, pts, q, out, f->cap, true);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(f->cap, &graph);
+    if (le == hipSuccess && e == hipSuccess) e = hipGraphInstantiate(&f->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    f->g_pts = pts;
+    f->g_q = q;
+    f->g_out = out;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_fmm_evaluate(sh_fmm *f, const double *pts, const double *q, double *out, unsigned flags,
+                          void *hip_stream)
+{
+    if (!f || !pts || !q || !out || (flags & ~SH_FMM_NO_GRAPH)) return SH_EINVAL;
+    std::lock_guard<std::mutex> lk(f->mu);
+    DeviceGuard g(f->ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (flags & SH_FMM_NO_GRAPH) return enqueue(f, pts, q, out, s, false) == hipSuccess ? SH_OK : SH_EDEVICE;
+    if (!f->exec || f->g_pts != pts || f->g_q != q || f->g_out != out) {
+        if (capture(f, pts, q, out) != hipSuccess) {
+            (void)hipGetLastError();
+            return SH_EDEVICE;
+        }
+    }
+    return hipGraphLaunch(f->exec, s) == hipSuccess ? SH_OK : SH_EDEVICE;
 }
 
 sh_status sh_fmm_describe(const sh_fmm *f, int64_t *counts)

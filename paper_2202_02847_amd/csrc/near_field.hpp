@@ -1,4 +1,4 @@
-// Host-side launcher of the near-field kernel (k_aux.hip), used by the FMM driver.
+// Host-side launchers of the near-field and fill kernels (k_aux.hip), used by the FMM driver.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -11,5 +11,11 @@ namespace shfmm {
 // target into out (4 doubles per particle; flags bit 0: accumulate, else overwrite).
 hipError_t launch_p2p(int64_t count, int64_t npts, const double *pts, const double *q, const int32_t *nbr,
                       double *out, unsigned flags, hipStream_t s);
+
+// Sets n doubles to zero with a kernel (a graph-capturable fill: no memset node).
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+
+// out[i] += sum over k < K of parts[k * stride + i] for i < n.
+hipError_t launch_add_parts(double *out, const double *parts, int K, int64_t n, int64_t stride, hipStream_t s);
 
 }  // namespace shfmm

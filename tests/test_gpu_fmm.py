@@ -120,13 +120,13 @@ def _oracle_fmm(orc, P, levels, origin, width, pts, q):
     return (far + near).reshape(-1, 4)
 
 
-def _gpu_fmm(ctx, P, levels, origin, width, pts, q):
+def _gpu_fmm(ctx, P, levels, origin, width, pts, q, flags=0):
     torch, dev = torch_dev()
     f = sh.Fmm(ctx, P, levels, origin, width, q.shape[1])
     d_p = torch.from_numpy(np.ascontiguousarray(pts.reshape(-1, 3))).to(dev)
     d_q = torch.from_numpy(np.ascontiguousarray(q.reshape(-1))).to(dev)
     d_o = torch.full((q.size, 4), np.nan, dtype=torch.float64, device=dev)
-    f.evaluate(d_p, d_q, d_o)
+    f.evaluate(d_p, d_q, d_o, flags)
     torch.cuda.synchronize()
     desc = f.describe()
     f.close()
@@ -137,12 +137,13 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+@pytest.mark.parametrize("flags", [0, sh.SH_FMM_NO_GRAPH], ids=["graph", "eager"])
 @pytest.mark.parametrize("P,levels,npts", [(6, 2, 5), (10, 3, 9), (17, 3, 3)])
-def test_fmm_matches_oracle_composition(ctx, orc, P, levels, npts):
+def test_fmm_matches_oracle_composition(ctx, orc, P, levels, npts, flags):
     origin, width = (-0.3, 0.1, 0.25), 2.0
-    print(f"[fmm] P={P} levels={levels} npts={npts}", flush=True)
+    print(f"[fmm] P={P} levels={levels} npts={npts} flags={flags}", flush=True)
     pts, q = _particles(levels, npts, origin, width, seed=P * 10 + levels)
-    got, desc = _gpu_fmm(ctx, P, levels, origin, width, pts, q)
+    got, desc = _gpu_fmm(ctx, P, levels, origin, width, pts, q, flags)
     assert np.isfinite(got).all()
     ref = _oracle_fmm(orc, P, levels, origin, width, pts, q)
     assert _rel(got[:, 0], ref[:, 0]) <= 1e-11
@@ -165,6 +166,33 @@ def test_fmm_truncation_error_falls_with_order(ctx):
         assert b[0] < a[0] and b[1] < a[1]
     # the CPU composition of the same method gives 2.5e-7 and 8.4e-8 at P = 16
     assert errs[-1][0] < 1e-5 and errs[-1][1] < 1e-5
+
+
+def test_fmm_graph_replays_match_eager(ctx):
+    """The captured graph, replayed several times with eager evaluations of other inputs on
+    the same handle in between, gives the eager result bit for bit every time."""
+    torch, dev = torch_dev()
+    P, levels, npts = 10, 3, 9
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=77)
+    _, q2 = _particles(levels, npts, origin, width, seed=78)
+    f = sh.Fmm(ctx, P, levels, origin, width, npts)
+    d_p = torch.from_numpy(np.ascontiguousarray(pts.reshape(-1, 3))).to(dev)
+    d_q = torch.from_numpy(np.ascontiguousarray(q.reshape(-1))).to(dev)
+    d_q2 = torch.from_numpy(np.ascontiguousarray(q2.reshape(-1))).to(dev)
+    d_o = torch.empty((q.size, 4), dtype=torch.float64, device=dev)
+    d_o2 = torch.empty_like(d_o)
+    f.evaluate(d_p, d_q, d_o, sh.SH_FMM_NO_GRAPH)
+    torch.cuda.synchronize()
+    eager = d_o.cpu().numpy().copy()
+    for rep in range(4):
+        d_o.fill_(np.nan)
+        f.evaluate(d_p, d_q, d_o)  # captured on the first pass, replayed after
+        torch.cuda.synchronize()
+        assert np.array_equal(d_o.cpu().numpy(), eager), rep
+        f.evaluate(d_p, d_q2, d_o2, sh.SH_FMM_NO_GRAPH)  # other work on the same pools
+        torch.cuda.synchronize()
+    f.close()
 
 
 def test_fmm_rejects_bad_arguments(ctx):
