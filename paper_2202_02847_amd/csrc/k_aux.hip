@@ -112,22 +112,30 @@ __global__ __launch_bounds__(64) void k_m2l_naive(TransArgs a)
     }
 }
 
-// one wavefront per cluster; lane m accumulates column m of sum_j q_j R(y_j - c)
+// One wavefront per cluster.  The 64 lanes form G = 64 / P groups of P lanes; lane (g, m)
+// takes the points j = g, g + G, ... and accumulates column m of sum_j q_j R(y_j - c) into LDS
+// copy g (the diagonal R_m^m takes m steps and the column P - 1 - m, so every lane does about
+// P steps per point); the G copies are added at the end.
 __global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *centres, int64_t npts,
                                             const double *pts, const double *q, double *Mout, int64_t ldM)
 {
-    extern __shared__ double accm[];  // P(P+1)
+    extern __shared__ double accm[];  // G copies of P(P+1)
     const int lane = threadIdx.x;
+    const int S = P * (P + 1);
+    const int G = P <= 64 ? 64 / P : 1;
+    const int g = lane / P, m0 = lane - g * P;
+    const bool active = g < G;
     for (int64_t c = blockIdx.x; c < count; c += gridDim.x) {
-        for (int i = lane; i < P * (P + 1); i += 64) accm[i] = 0.0;
+        for (int i = lane; i < G * S; i += 64) accm[i] = 0.0;
         __syncthreads();
         const double cx = centres[3 * c], cy = centres[3 * c + 1], cz = centres[3 * c + 2];
-        for (int64_t j = 0; j < npts; ++j) {
+        double *acc = accm + (active ? g : 0) * S;
+        for (int64_t j = active ? g : npts; j < npts; j += G) {
             const double *pj = pts + 3 * (npts * c + j);
             const double x = pj[0] - cx, y = pj[1] - cy, z = pj[2] - cz;
             const double r2 = x * x + y * y + z * z;
             const double qj = q[npts * c + j];
-            for (int m = lane; m < P; m += 64) {
+            for (int m = m0; m < P; m += 64) {
                 // R_m^m = prod_{i=1}^{m} (x+iy)/(2i)
                 double dr = 1.0, di = 0.0;
                 for (int i = 1; i <= m; ++i) {
@@ -137,8 +145,8 @@ __global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *
                 }
                 // (n^2 - m^2) R_n^m = (2n-1) z R_{n-1}^m - |r|^2 R_{n-2}^m
                 double ar = dr, ai = di, br = 0.0, bi = 0.0;  // R_{n-1}, R_{n-2}
-                accm[solid_pos(m, m)] += qj * ar;
-                accm[solid_pos(m, m) + 1] += qj * ai;
+                acc[solid_pos(m, m)] += qj * ar;
+                acc[solid_pos(m, m) + 1] += qj * ai;
                 for (int n = m + 1; n < P; ++n) {
                     const double d = (double)n * n - (double)m * m;
                     const double cr = ((2 * n - 1) * z * ar - r2 * br) / d;
@@ -147,18 +155,20 @@ __global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *
                     bi = ai;
                     ar = cr;
                     ai = ci;
-                    accm[solid_pos(n, m)] += qj * ar;
-                    accm[solid_pos(n, m) + 1] += qj * ai;
+                    acc[solid_pos(n, m)] += qj * ar;
+                    acc[solid_pos(n, m) + 1] += qj * ai;
                 }
             }
         }
         __syncthreads();
         double *Mo = Mout + c * ldM;
-        for (int i = lane; i < P * (P + 1); i += 64) {
+        for (int i = lane; i < S; i += 64) {
             int n = (int)((sqrtf(4.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
             while ((n + 1) * (n + 2) <= i) ++n;
             while (n * (n + 1) > i) --n;
-            Mo[i] = (i == n * (n + 1) + 1) ? 0.0 : accm[i];
+            double v = 0.0;
+            for (int k = 0; k < G; ++k) v += accm[k * S + i];
+            Mo[i] = (i == n * (n + 1) + 1) ? 0.0 : v;
         }
         __syncthreads();
     }
@@ -178,6 +188,14 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
                                              int64_t npts, const double *pts, const double *Lpool,
                                              int64_t ldL, double *out, unsigned flags)
 {
+    // recurrence constants, shared by the workgroup: rc[k P + j] = 1/(k^2 - j^2) (k > j),
+    // rc[j P + j] = 1/(2j) (j > 0)
+    extern __shared__ double rc[];
+    for (int i = threadIdx.x; i < P * P; i += 256) {
+        const int k = i / P, j = i - k * P;
+        rc[i] = (k > j) ? 1.0 / ((double)k * k - (double)j * j) : ((k == j && j > 0) ? 0.5 / (double)j : 0.0);
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t ntask = count * chunks;
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
         double dr = 1.0, di = 0.0;  // R_j^j
         for (int j = 0; j < P; ++j) {
             if (j > 0) {
-                const double f = 0.5 / (double)j;
+                const double f = rc[j * P + j];
                 const double nr = (x * dr - y * di) * f, ni = (x * di + y * dr) * f;
                 dr = nr;
                 di = ni;
@@ -204,7 +222,7 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
             double cp = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
             for (int k = j; k < P; ++k) {
                 if (k > j) {
-                    const double inv = 1.0 / ((double)k * k - (double)j * j);
+                    const double inv = rc[k * P + j];
                     const double tz = (double)(2 * k - 1) * z;
                     const double nr = (tz * ar - r2 * br) * inv, ni = (tz * ai - r2 * bi) * inv;
                     br = ar;
@@ -350,7 +368,8 @@ hipError_t launch_p2m(int P, int64_t count, const double *centres, int64_t npts,
                       const double *q, double *M, int64_t ldM, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    const size_t smem = (size_t)P * (P + 1) * sizeof(double);
+    const int G = P <= 64 ? 64 / P : 1;
+    const size_t smem = (size_t)G * P * (P + 1) * sizeof(double);
     const int64_t grid64 = count < (1 << 20) ? count : (1 << 20);
     hipLaunchKernelGGL(k_p2m, dim3((unsigned)grid64), dim3(64), smem, s, P, count, centres, npts, pts, q, M, ldM);
     return hipGetLastError();
@@ -363,8 +382,8 @@ hipError_t launch_l2p(int P, int64_t count, const double *centres, int64_t npts,
     const int64_t chunks = (npts + 63) / 64;
     const int64_t blocks = (count * chunks + 3) / 4;
     const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
-    hipLaunchKernelGGL(k_l2p, dim3((unsigned)grid64), dim3(256), 0, s, P, count, chunks, centres, npts, pts, L, ldL,
-                       out, flags);
+    hipLaunchKernelGGL(k_l2p, dim3((unsigned)grid64), dim3(256), (size_t)P * P * sizeof(double), s, P, count, chunks,
+                       centres, npts, pts, L, ldL, out, flags);
     return hipGetLastError();
 }
 
