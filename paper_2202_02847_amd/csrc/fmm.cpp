@@ -11,17 +11,18 @@
 // Launch grouping (each translation call needs distinct output solids when it accumulates):
 //   * M2M, level l -> l-1: one call per child octant (each parent has one child per octant);
 //     the first overwrites the parents, the other seven accumulate.
-//   * M2L at level l >= 2: one call per offset d in [-3, 3]^3 \ [-1, 1]^3 (316 offsets); the
-//     pairs (b + d -> b) of an offset have distinct targets b.  The pair is in the interaction
-//     list of b when the parents of b and b + d are neighbours (or equal).  A level's calls
-//     are split into kGroups groups of about equal work; group g accumulates into its own
-//     partial pool, so the groups run concurrently (graph branches), and one kernel adds the
-//     partial pools into the local expansions.
+//   * M2L at level l >= 2, target-major: the pairs (source b + d -> target b), d in
+//     [-3, 3]^3 \ [-1, 1]^3 with the parents of b and b + d neighbours (or equal), are listed
+//     target by target, so each target's pairs are contiguous.  One indexed launch per chunk
+//     of targets writes every translation to its own scratch solid, and a segmented sum adds
+//     each target's run into its local expansion: a few large launches per level instead of
+//     one small launch per offset (whose targets overlap across offsets).
 //   * L2L, level l -> l+1: one call per child octant, accumulating into the children.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -39,10 +40,16 @@ struct FmmCall {
     int level_in, level_out;
     int64_t count;
     int64_t off;  // first pair in the shared src / dst / r arrays
-    int group;    // M2L: partial pool the call accumulates into
 };
 
-constexpr int kGroups = 8;
+// M2L of the targets [tb, te) of one level: pairs [off, off + count) of the shared arrays.
+struct M2lChunk {
+    int level;
+    int64_t off, count;
+    int64_t tb, te;
+};
+
+constexpr int64_t kScratchBytes = (int64_t)1 << 30;  // M2L scratch solids per chunk
 
 }  // namespace
 
@@ -54,11 +61,16 @@ struct sh_fmm {
     double width = 1;
     std::vector<int64_t> lvl_off;  // first box of level l in the M / L pools
     int64_t nbox = 0;
-    std::vector<FmmCall> up, m2l, down;
+    std::vector<FmmCall> up, down;
+    std::vector<M2lChunk> m2l;
+    std::vector<int64_t> seg_off;  // level l's target offsets start at seg + seg_off[l]
+    int64_t chunk_cap = 0;         // scratch solids
     // device memory: one allocation
     void *mem = nullptr;
     double *M = nullptr, *L = nullptr;  // pools: nbox solids of P(P+1) reals
-    double *part = nullptr;             // kGroups partial pools of levels 2..L
+    double *scratch = nullptr;          // chunk_cap solids: one M2L result each
+    int64_t *iota = nullptr;            // 0 .. chunk_cap - 1 (scratch slots)
+    int64_t *seg = nullptr;             // per level: first pair of every target, and the end
     int64_t *src = nullptr, *dst = nullptr;
     double *r = nullptr;
     double *leaf_centres = nullptr;
@@ -96,7 +108,8 @@ struct HostPlan {
 
 inline int64_t fdiv2(int64_t a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
 
-void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<int32_t> &nbr)
+void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<double> &centres,
+           std::vector<int32_t> &nbr)
 {
     const int Lv = f->levels;
     // upward: children at level l (octant o) -> parents at level l - 1
@@ -105,7 +118,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
         const double w = f->width / (double)n;
         for (int o = 0; o < 8; ++o) {
             const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_M2M, l, l - 1, 0, (int64_t)hp.src.size(), 0};
+            FmmCall c{SH_M2M, l, l - 1, 0, (int64_t)hp.src.size()};
             for (int64_t px = 0; px < np; ++px)
                 for (int64_t py = 0; py < np; ++py)
                     for (int64_t pz = 0; pz < np; ++pz)
@@ -115,52 +128,45 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
             f->up.push_back(c);
         }
     }
-    // M2L at levels 2..L: offsets d with max |d_i| >= 2, parents neighbours
+    // M2L at levels 2..L, target by target: offsets d with max |d_i| >= 2, parents neighbours
+    const int64_t S = (int64_t)f->P * (f->P + 1);
+    f->chunk_cap = std::max<int64_t>(189, kScratchBytes / (S * (int64_t)sizeof(double)));
+    f->seg_off.assign(Lv + 1, 0);
     for (int l = 2; l <= Lv; ++l) {
         const int64_t n = (int64_t)1 << l;
         const double w = f->width / (double)n;
-        for (int dx = -3; dx <= 3; ++dx)
-            for (int dy = -3; dy <= 3; ++dy)
-                for (int dz = -3; dz <= 3; ++dz) {
-                    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-                    FmmCall c{SH_M2L, l, l, 0, (int64_t)hp.src.size(), 0};
-                    for (int64_t ix = 0; ix < n; ++ix) {
-                        const int64_t sx = ix + dx;
-                        if (sx < 0 || sx >= n) continue;
-                        const int64_t ax = fdiv2(sx) - fdiv2(ix);
-                        if (ax < -1 || ax > 1) continue;
-                        for (int64_t iy = 0; iy < n; ++iy) {
-                            const int64_t sy = iy + dy;
-                            if (sy < 0 || sy >= n) continue;
-                            const int64_t ay = fdiv2(sy) - fdiv2(iy);
-                            if (ay < -1 || ay > 1) continue;
-                            for (int64_t iz = 0; iz < n; ++iz) {
-                                const int64_t sz = iz + dz;
-                                if (sz < 0 || sz >= n) continue;
-                                const int64_t az = fdiv2(sz) - fdiv2(iz);
-                                if (az < -1 || az > 1) continue;
+        f->seg_off[l] = (int64_t)seg.size();
+        M2lChunk ck{l, (int64_t)hp.src.size(), 0, 0, 0};
+        for (int64_t ix = 0; ix < n; ++ix)
+            for (int64_t iy = 0; iy < n; ++iy)
+                for (int64_t iz = 0; iz < n; ++iz) {
+                    const int64_t b = box_index(n, ix, iy, iz);
+                    const int64_t first = (int64_t)hp.src.size();
+                    seg.push_back(first);
+                    for (int dx = -3; dx <= 3; ++dx)
+                        for (int dy = -3; dy <= 3; ++dy)
+                            for (int dz = -3; dz <= 3; ++dz) {
+                                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+                                const int64_t sx = ix + dx, sy = iy + dy, sz = iz + dz;
+                                if (sx < 0 || sy < 0 || sz < 0 || sx >= n || sy >= n || sz >= n) continue;
+                                if (std::abs(fdiv2(sx) - fdiv2(ix)) > 1 || std::abs(fdiv2(sy) - fdiv2(iy)) > 1 ||
+                                    std::abs(fdiv2(sz) - fdiv2(iz)) > 1)
+                                    continue;
                                 // r = x_B - x_A = centre(target) - centre(source) = -d w
-                                hp.add(box_index(n, sx, sy, sz), box_index(n, ix, iy, iz), -dx * w, -dy * w, -dz * w);
+                                hp.add(box_index(n, sx, sy, sz), b, -dx * w, -dy * w, -dz * w);
                             }
-                        }
+                    // close the chunk before this target if its pairs would not fit
+                    if ((int64_t)hp.src.size() - ck.off > f->chunk_cap) {
+                        ck.count = first - ck.off;
+                        ck.te = b;
+                        f->m2l.push_back(ck);
+                        ck = M2lChunk{l, first, 0, b, 0};
                     }
-                    c.count = (int64_t)hp.src.size() - c.off;
-                    if (c.count > 0) f->m2l.push_back(c);
                 }
-        // groups of about equal work: each call to the least loaded group, largest first
-        std::vector<size_t> idx;
-        for (size_t i = 0; i < f->m2l.size(); ++i)
-            if (f->m2l[i].level_in == l) idx.push_back(i);
-        std::stable_sort(idx.begin(), idx.end(),
-                         [&](size_t a, size_t b) { return f->m2l[a].count > f->m2l[b].count; });
-        int64_t load[kGroups] = {0};
-        for (size_t i : idx) {
-            int g = 0;
-            for (int k = 1; k < kGroups; ++k)
-                if (load[k] < load[g]) g = k;
-            f->m2l[i].group = g;
-            load[g] += f->m2l[i].count;
-        }
+        seg.push_back((int64_t)hp.src.size());
+        ck.count = (int64_t)hp.src.size() - ck.off;
+        ck.te = boxes_at(l);
+        f->m2l.push_back(ck);
     }
     // downward: parents at level l -> children at level l + 1 (octant o), from level 2
     for (int l = 2; l < Lv; ++l) {
@@ -168,7 +174,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<double> &centres, std::vector<in
         const double w = f->width / (double)n;
         for (int o = 0; o < 8; ++o) {
             const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size(), 0};
+            FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size()};
             for (int64_t px = 0; px < np; ++px)
                 for (int64_t py = 0; py < np; ++py)
                     for (int64_t pz = 0; pz < np; ++pz)
@@ -227,15 +233,20 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
     for (int l = 0; l <= levels; ++l) f->lvl_off[l + 1] = f->lvl_off[l] + boxes_at(l);
     f->nbox = f->lvl_off[levels + 1];
     HostPlan hp;
+    std::vector<int64_t> seg;
     std::vector<double> centres;
     std::vector<int32_t> nbr;
     try {
-        build(f, hp, centres, nbr);
+        build(f, hp, seg, centres, nbr);
     } catch (...) {
         delete f;
         return SH_ENOMEM;
     }
     f->npairs = (int64_t)hp.src.size();
+    // scratch for the largest chunk built (chunks were cut at kScratchBytes)
+    int64_t biggest = 1;
+    for (const M2lChunk &c : f->m2l) biggest = std::max(biggest, c.count);
+    f->chunk_cap = biggest;
     const int64_t S = (int64_t)P * (P + 1);
     auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t bM = up256(sizeof(double) * (size_t)(f->nbox * S));
@@ -248,9 +259,10 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
         delete f;
         return SH_EDEVICE;
     }
-    const int64_t part_reals = (f->nbox - f->lvl_off[2]) * S;  // levels 2..L
-    const size_t bP = up256(sizeof(double) * (size_t)(kGroups * part_reals));
-    if (hipMalloc(&f->mem, 2 * bM + 2 * bI + bR + bC + bN + bP) != hipSuccess) {
+    const size_t bX = up256(sizeof(double) * (size_t)(f->chunk_cap * S));
+    const size_t bT = up256(sizeof(int64_t) * (size_t)f->chunk_cap);
+    const size_t bG = up256(sizeof(int64_t) * seg.size());
+    if (hipMalloc(&f->mem, 2 * bM + 2 * bI + bR + bC + bN + bX + bT + bG) != hipSuccess) {
         (void)hipGetLastError();
         delete f;
         return SH_ENOMEM;
@@ -263,13 +275,19 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
     f->r = reinterpret_cast<double *>(p + 2 * bM + 2 * bI);
     f->leaf_centres = reinterpret_cast<double *>(p + 2 * bM + 2 * bI + bR);
     f->nbr = reinterpret_cast<int32_t *>(p + 2 * bM + 2 * bI + bR + bC);
-    f->part = reinterpret_cast<double *>(p + 2 * bM + 2 * bI + bR + bC + bN);
+    f->scratch = reinterpret_cast<double *>(p + 2 * bM + 2 * bI + bR + bC + bN);
+    f->iota = reinterpret_cast<int64_t *>(p + 2 * bM + 2 * bI + bR + bC + bN + bX);
+    f->seg = reinterpret_cast<int64_t *>(p + 2 * bM + 2 * bI + bR + bC + bN + bX + bT);
+    std::vector<int64_t> iota((size_t)f->chunk_cap);
+    for (int64_t i = 0; i < f->chunk_cap; ++i) iota[(size_t)i] = i;
     bool ok = hipMemcpy(f->src, hp.src.data(), sizeof(int64_t) * hp.src.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(f->dst, hp.dst.data(), sizeof(int64_t) * hp.dst.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(f->r, hp.r.data(), sizeof(double) * hp.r.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(f->leaf_centres, centres.data(), sizeof(double) * centres.size(), hipMemcpyHostToDevice) ==
                   hipSuccess &&
-              hipMemcpy(f->nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(f->nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(f->iota, iota.data(), sizeof(int64_t) * iota.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(f->seg, seg.data(), sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         (void)hipFree(f->mem);
         delete f;
@@ -300,9 +318,8 @@ namespace {
 hipError_t status_to_hip(sh_status st) { return st == SH_OK ? hipSuccess : hipErrorUnknown; }
 
 // Enqueues one evaluation on stream s.  With fork (graph capture), the near field runs on
-// side[0] from the start and M2L group g on side[1 + g]: the near field writes the output
-// first (overwrite) while the far field is computed, and L2P adds the far field last.  The
-// calls of one group stay in order (their targets overlap across offsets).
+// side[0] from the start: it writes the output first (overwrite) while the far field is
+// computed, and L2P adds the far field last.
 hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, hipStream_t s, bool fork)
 {
     const int P = f->P, Lv = f->levels;
@@ -310,8 +327,6 @@ hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, h
     const int64_t nleaf = boxes_at(Lv);
     double *Mleaf = f->M + f->lvl_off[Lv] * S;
     double *Lleaf = f->L + f->lvl_off[Lv] * S;
-    double *L2 = f->L + f->lvl_off[2] * S;  // levels 2..L
-    const int64_t part_reals = (f->nbox - f->lvl_off[2]) * S;
     hipError_t e;
     hipStream_t near = s;
     if (fork) {
@@ -321,44 +336,32 @@ hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, h
     }
     if ((e = shfmm::launch_p2p(nleaf, f->npts, pts, q, f->nbr, out, 0u, near)) != hipSuccess) return e;
     if ((e = shfmm::launch_p2m(P, nleaf, f->leaf_centres, f->npts, pts, q, Mleaf, S, s)) != hipSuccess) return e;
-    // pool_out + (level_out's first box - out_first) solids: the output level's solids
-    auto run = [&](const FmmCall &c, const double *pool_in, double *pool_out, int64_t out_first, unsigned flags,
-                   hipStream_t st) {
+    auto run = [&](const FmmCall &c, unsigned flags, double *pool) {
         return status_to_hip(shfmm::translate_device(f->ctx, c.op, SH_F64, P, P, c.count, f->r + 3 * c.off,
-                                                     f->src + c.off, pool_in + f->lvl_off[c.level_in] * S, S,
-                                                     f->dst + c.off,
-                                                     pool_out + (f->lvl_off[c.level_out] - out_first) * S, S, flags,
-                                                     st));
+                                                     f->src + c.off, pool + f->lvl_off[c.level_in] * S, S,
+                                                     f->dst + c.off, pool + f->lvl_off[c.level_out] * S, S, flags,
+                                                     s));
     };
     // upward pass: the first octant of a level overwrites its parents
     for (size_t i = 0; i < f->up.size(); ++i)
-        if ((e = run(f->up[i], f->M, f->M, 0, (i % 8 == 0) ? 0u : SH_ACCUMULATE, s)) != hipSuccess) return e;
-    // local expansions and the partial pools start at zero at levels 2..L
-    if ((e = shfmm::launch_zero(L2, part_reals, s)) != hipSuccess) return e;
-    if ((e = shfmm::launch_zero(f->part, kGroups * part_reals, s)) != hipSuccess) return e;
-    if (fork) {
-        if ((e = hipEventRecord(f->ev[1], s)) != hipSuccess) return e;
-        for (int g = 0; g < kGroups; ++g)
-            if ((e = hipStreamWaitEvent(f->side[1 + g], f->ev[1], 0)) != hipSuccess) return e;
-    }
-    // the partial pool of group g stands in for the L pool of levels 2..L
-    for (const FmmCall &c : f->m2l) {
-        double *pool = f->part + c.group * part_reals;
-        if ((e = run(c, f->M, pool, f->lvl_off[2], SH_ACCUMULATE, fork ? f->side[1 + c.group] : s)) != hipSuccess)
+        if ((e = run(f->up[i], (i % 8 == 0) ? 0u : SH_ACCUMULATE, f->M)) != hipSuccess) return e;
+    // M2L: every translation of a chunk into its scratch solid, then each target's run summed
+    // into its local expansion (overwriting: every target of levels 2..L is in one chunk)
+    for (const M2lChunk &c : f->m2l) {
+        const int l = c.level;
+        if ((e = status_to_hip(shfmm::translate_device(f->ctx, SH_M2L, SH_F64, P, P, c.count, f->r + 3 * c.off,
+                                                       f->src + c.off, f->M + f->lvl_off[l] * S, S, f->iota,
+                                                       f->scratch, S, 0u, s))) != hipSuccess)
+            return e;
+        if ((e = shfmm::launch_seg_sum(f->L + f->lvl_off[l] * S, S, f->seg + f->seg_off[l], c.tb, c.te, c.off,
+                                       f->scratch, s)) != hipSuccess)
             return e;
     }
-    if (fork) {
-        for (int g = 0; g < kGroups; ++g) {
-            if ((e = hipEventRecord(f->ev[2 + g], f->side[1 + g])) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(s, f->ev[2 + g], 0)) != hipSuccess) return e;
-        }
-    }
-    if ((e = shfmm::launch_add_parts(L2, f->part, kGroups, part_reals, part_reals, s)) != hipSuccess) return e;
     for (const FmmCall &c : f->down)
-        if ((e = run(c, f->L, f->L, 0, SH_ACCUMULATE, s)) != hipSuccess) return e;
+        if ((e = run(c, SH_ACCUMULATE, f->L)) != hipSuccess) return e;
     if (fork) {
-        if ((e = hipEventRecord(f->ev[2 + kGroups], f->side[0])) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(s, f->ev[2 + kGroups], 0)) != hipSuccess) return e;
+        if ((e = hipEventRecord(f->ev[1], f->side[0])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, f->ev[1], 0)) != hipSuccess) return e;
     }
     return shfmm::launch_l2p(P, nleaf, f->leaf_centres, f->npts, pts, Lleaf, S, out, 1u, s);
 }
@@ -372,12 +375,12 @@ hipError_t capture(sh_fmm *f, const double *pts, const double *q, double *out)
     }
     if (!f->cap) {
         if ((e = hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking)) != hipSuccess) return e;
-        for (int i = 0; i < 1 + kGroups; ++i) {
+        {
             hipStream_t st;
             if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
             f->side.push_back(st);
         }
-        for (int i = 0; i < 3 + kGroups; ++i) {
+        for (int i = 0; i < 2; ++i) {
             hipEvent_t ev;
             if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
             f->ev.push_back(ev);
@@ -424,7 +427,7 @@ sh_status sh_fmm_describe(const sh_fmm *f, int64_t *counts)
     if (!f || !counts) return SH_EINVAL;
     int64_t t[3] = {0, 0, 0};
     for (const FmmCall &c : f->up) t[0] += c.count;
-    for (const FmmCall &c : f->m2l) t[1] += c.count;
+    for (const M2lChunk &c : f->m2l) t[1] += c.count;
     for (const FmmCall &c : f->down) t[2] += c.count;
     counts[0] = t[0];
     counts[1] = t[1];

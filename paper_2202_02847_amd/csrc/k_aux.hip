@@ -335,7 +335,32 @@ __global__ __launch_bounds__(256) void k_add_parts(double *out, const double *pa
     }
 }
 
+// Segmented sum: L[b] = sum of the solids scratch[t - base] for t in [seg[b], seg[b + 1]),
+// for targets b in [tb, te); one thread per (target, coefficient), coalesced over coefficients.
+__global__ __launch_bounds__(256) void k_seg_sum(double *L, int64_t S, const int64_t *seg, int64_t tb, int64_t te,
+                                                 int64_t base, const double *scratch)
+{
+    const int64_t n = (te - tb) * S;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * 256) {
+        const int64_t b = tb + idx / S, i = idx - (idx / S) * S;
+        double v = 0.0;
+        for (int64_t t = seg[b] - base; t < seg[b + 1] - base; ++t) v += scratch[t * S + i];
+        L[b * S + i] = v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_seg_sum(double *L, int64_t S, const int64_t *seg, int64_t tb, int64_t te, int64_t base,
+                          const double *scratch, hipStream_t s)
+{
+    const int64_t n = (te - tb) * S;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, L, S, seg, tb, te,
+                       base, scratch);
+    return hipGetLastError();
+}
 
 hipError_t launch_add_parts(double *out, const double *parts, int K, int64_t n, int64_t stride, hipStream_t s)
 {
