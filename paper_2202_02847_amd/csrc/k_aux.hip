@@ -320,21 +320,6 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t count, int64_t chunks, int6
     }
 }
 
-__global__ __launch_bounds__(256) void k_zero(double *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0;
-}
-
-// out[i] += sum_{k < K} parts[k * stride + i], i < n
-__global__ __launch_bounds__(256) void k_add_parts(double *out, const double *parts, int K, int64_t n, int64_t stride)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        double v = out[i];
-        for (int k = 0; k < K; ++k) v += parts[(int64_t)k * stride + i];
-        out[i] = v;
-    }
-}
-
 // Segmented sum: L[b] = sum of the solids scratch[t - base] for t in [seg[b], seg[b + 1]),
 // for targets b in [tb, te); one thread per (target, coefficient), coalesced over coefficients.
 __global__ __launch_bounds__(256) void k_seg_sum(double *L, int64_t S, const int64_t *seg, int64_t tb, int64_t te,
@@ -359,23 +344,6 @@ hipError_t launch_seg_sum(double *L, int64_t S, const int64_t *seg, int64_t tb, 
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, L, S, seg, tb, te,
                        base, scratch);
-    return hipGetLastError();
-}
-
-hipError_t launch_add_parts(double *out, const double *parts, int K, int64_t n, int64_t stride, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_add_parts, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, out, parts, K, n,
-                       stride);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

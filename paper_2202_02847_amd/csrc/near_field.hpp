@@ -1,4 +1,5 @@
-// Host-side launchers of the near-field and fill kernels (k_aux.hip), used by the FMM driver.
+// Host-side launchers of the near-field and segmented-sum kernels (k_aux.hip), used by the FMM
+// driver.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -12,15 +13,9 @@ namespace shfmm {
 hipError_t launch_p2p(int64_t count, int64_t npts, const double *pts, const double *q, const int32_t *nbr,
                       double *out, unsigned flags, hipStream_t s);
 
-// Sets n doubles to zero with a kernel (a graph-capturable fill: no memset node).
-hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
-
 // L[b] = sum of the solids scratch[t - base], t in [seg[b], seg[b+1]), for b in [tb, te)
 // (S reals per solid).
 hipError_t launch_seg_sum(double *L, int64_t S, const int64_t *seg, int64_t tb, int64_t te, int64_t base,
                           const double *scratch, hipStream_t s);
-
-// out[i] += sum over k < K of parts[k * stride + i] for i < n.
-hipError_t launch_add_parts(double *out, const double *parts, int K, int64_t n, int64_t stride, hipStream_t s);
 
 }  // namespace shfmm
