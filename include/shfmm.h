@@ -389,6 +389,13 @@ typedef struct sh_fmm sh_fmm;
  * Errors: SH_EINVAL, SH_EORDER, SH_ENOMEM, SH_EDEVICE. */
 sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], double width,
                         int64_t npts, sh_fmm **out);
+/* Variable order per level (input order differing from output order, Section 1.1):
+ * orders[l - 2] is the expansion order of level l = 2..levels (levels - 1 entries; levels 0
+ * and 1 carry no expansions).  M2M from level l to l - 1 and L2L from l to l + 1 translate
+ * between the two levels' orders; M2L stays within a level; the leaves use orders[levels - 2]
+ * for P2M and L2P.  Errors as sh_fmm_create (SH_EINVAL for a NULL orders). */
+sh_status sh_fmm_create_orders(sh_ctx *ctx, int levels, const int *orders, const double origin[3],
+                               double width, int64_t npts, sh_fmm **out);
 void sh_fmm_destroy(sh_fmm *fmm);
 
 /* One evaluation on device pointers, stream-ordered: pts (N x 3, leaf by leaf), charges q

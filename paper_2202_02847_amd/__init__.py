@@ -59,6 +59,7 @@ _SIGS = {
     "sh_p2m_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _vp, _c_i64, _vp]),
     "sh_l2p_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_u32, _vp]),
     "sh_fmm_create": (_c_i32, [_vp, _c_i32, _c_i32, _vp, ctypes.c_double, _c_i64, _vp]),
+    "sh_fmm_create_orders": (_c_i32, [_vp, _c_i32, _vp, _vp, ctypes.c_double, _c_i64, _vp]),
     "sh_fmm_destroy": (None, [_vp]),
     "sh_fmm_evaluate": (_c_i32, [_vp, _vp, _vp, _vp, _c_u32, _vp]),
     "sh_fmm_describe": (_c_i32, [_vp, _vp]),
@@ -566,6 +567,18 @@ def sh_fmm_create(ctx, P, levels, origin, width, npts):
     return h
 
 
+def sh_fmm_create_orders(ctx, levels, orders, origin, width, npts):
+    """Per-level orders: orders[l - 2] for level l = 2..levels.  Returns the sh_fmm handle."""
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    ords = (ctypes.c_int * len(orders))(*[int(v) for v in orders])
+    if len(orders) != int(levels) - 1:
+        raise ValueError("orders needs one entry per level 2..levels")
+    h = ctypes.c_void_p()
+    _check(lib().sh_fmm_create_orders(_h(ctx), int(levels), ords, o, float(width), int(npts), ctypes.byref(h)),
+           "sh_fmm_create_orders")
+    return h
+
+
 def sh_fmm_destroy(h):
     lib().sh_fmm_destroy(h)
 
@@ -584,9 +597,15 @@ def sh_fmm_describe(h):
 class Fmm:
     """Uniform-octree FMM handle (sh_fmm_*): P2M, M2M, M2L, L2L, L2P and P2P on the device."""
 
-    def __init__(self, ctx, P, levels, origin, width, npts):
+    def __init__(self, ctx, P, levels, origin, width, npts, orders=None):
+        """orders (optional): the order of each level 2..levels; P is then ignored."""
         self._ctx = ctx
-        self._h = sh_fmm_create(ctx, P, levels, origin, width, npts)
+        self._h = None
+        if orders is None:
+            self._h = sh_fmm_create(ctx, P, levels, origin, width, npts)
+        else:
+            self._h = sh_fmm_create_orders(ctx, levels, orders, origin, width, npts)
+            P = orders[-1]
         self.P, self.levels, self.npts = int(P), int(levels), int(npts)
         self.n_particles = 8 ** self.levels * self.npts
 

@@ -55,20 +55,21 @@ constexpr int64_t kScratchBytes = (int64_t)1 << 30;  // M2L scratch solids per c
 
 struct sh_fmm {
     sh_ctx *ctx = nullptr;
-    int P = 0, levels = 0;
+    int P = 0, levels = 0;          // P: order of the leaves
+    std::vector<int> Pl;            // order of level l (levels 2..L)
+    std::vector<int64_t> roff;      // level l's solids start at roff[l] reals in the M / L pools
     int64_t npts = 0;
     double origin[3] = {0, 0, 0};
     double width = 1;
-    std::vector<int64_t> lvl_off;  // first box of level l in the M / L pools
-    int64_t nbox = 0;
     std::vector<FmmCall> up, down;
     std::vector<M2lChunk> m2l;
     std::vector<int64_t> seg_off;  // level l's target offsets start at seg + seg_off[l]
-    int64_t chunk_cap = 0;         // scratch solids
+    int64_t chunk_cap = 0;         // iota entries: pairs of the largest chunk
+    int64_t scratch_reals = 0;
     // device memory: one allocation
     void *mem = nullptr;
-    double *M = nullptr, *L = nullptr;  // pools: nbox solids of P(P+1) reals
-    double *scratch = nullptr;          // chunk_cap solids: one M2L result each
+    double *M = nullptr, *L = nullptr;  // pools: boxes of levels 2..L, P_l(P_l+1) reals each
+    double *scratch = nullptr;          // scratch_reals: one M2L result per solid
     int64_t *iota = nullptr;            // 0 .. chunk_cap - 1 (scratch slots)
     int64_t *seg = nullptr;             // per level: first pair of every target, and the end
     int64_t *src = nullptr, *dst = nullptr;
@@ -112,8 +113,9 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<doubl
            std::vector<int32_t> &nbr)
 {
     const int Lv = f->levels;
-    // upward: children at level l (octant o) -> parents at level l - 1
-    for (int l = Lv; l >= 1; --l) {
+    // upward: children at level l (octant o) -> parents at level l - 1 >= 2 (the multipoles
+    // of levels 0 and 1 have no interaction list to feed)
+    for (int l = Lv; l >= 3; --l) {
         const int64_t n = (int64_t)1 << l, np = n / 2;
         const double w = f->width / (double)n;
         for (int o = 0; o < 8; ++o) {
@@ -129,10 +131,10 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<doubl
         }
     }
     // M2L at levels 2..L, target by target: offsets d with max |d_i| >= 2, parents neighbours
-    const int64_t S = (int64_t)f->P * (f->P + 1);
-    f->chunk_cap = std::max<int64_t>(189, kScratchBytes / (S * (int64_t)sizeof(double)));
     f->seg_off.assign(Lv + 1, 0);
     for (int l = 2; l <= Lv; ++l) {
+        const int64_t S = (int64_t)f->Pl[l] * (f->Pl[l] + 1);
+        const int64_t cap = std::max<int64_t>(189, kScratchBytes / (S * (int64_t)sizeof(double)));
         const int64_t n = (int64_t)1 << l;
         const double w = f->width / (double)n;
         f->seg_off[l] = (int64_t)seg.size();
@@ -156,7 +158,7 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<doubl
                                 hp.add(box_index(n, sx, sy, sz), b, -dx * w, -dy * w, -dz * w);
                             }
                     // close the chunk before this target if its pairs would not fit
-                    if ((int64_t)hp.src.size() - ck.off > f->chunk_cap) {
+                    if ((int64_t)hp.src.size() - ck.off > cap) {
                         ck.count = first - ck.off;
                         ck.te = b;
                         f->m2l.push_back(ck);
@@ -211,27 +213,28 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<doubl
 
 extern "C" {
 
-sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], double width, int64_t npts,
-                        sh_fmm **out)
+sh_status sh_fmm_create_orders(sh_ctx *ctx, int levels, const int *orders, const double origin[3], double width,
+                               int64_t npts, sh_fmm **out)
 {
     if (!out) return SH_EINVAL;
     *out = nullptr;
-    if (!ctx || !origin || !(width > 0.0) || npts < 1 || levels < 2 || levels > SH_FMM_MAX_LEVELS)
+    if (!ctx || !orders || !origin || !(width > 0.0) || npts < 1 || levels < 2 || levels > SH_FMM_MAX_LEVELS)
         return SH_EINVAL;
-    if (P < 1 || P > ctx->max_order) return SH_EORDER;
+    for (int l = 2; l <= levels; ++l)
+        if (orders[l - 2] < 1 || orders[l - 2] > ctx->max_order) return SH_EORDER;
     if (boxes_at(levels) * npts > ((int64_t)1 << 31)) return SH_EINVAL;
     sh_fmm *f = new (std::nothrow) sh_fmm;
     if (!f) return SH_ENOMEM;
     f->ctx = ctx;
-    f->P = P;
     f->levels = levels;
+    f->Pl.assign(levels + 1, 0);
+    for (int l = 2; l <= levels; ++l) f->Pl[l] = orders[l - 2];
+    f->P = f->Pl[levels];
     f->npts = npts;
     std::memcpy(f->origin, origin, sizeof f->origin);
     f->width = width;
-    f->lvl_off.resize(levels + 2);
-    f->lvl_off[0] = 0;
-    for (int l = 0; l <= levels; ++l) f->lvl_off[l + 1] = f->lvl_off[l] + boxes_at(l);
-    f->nbox = f->lvl_off[levels + 1];
+    f->roff.assign(levels + 2, 0);
+    for (int l = 2; l <= levels; ++l) f->roff[l + 1] = f->roff[l] + boxes_at(l) * f->Pl[l] * (f->Pl[l] + 1);
     HostPlan hp;
     std::vector<int64_t> seg;
     std::vector<double> centres;
@@ -244,12 +247,14 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
     }
     f->npairs = (int64_t)hp.src.size();
     // scratch for the largest chunk built (chunks were cut at kScratchBytes)
-    int64_t biggest = 1;
-    for (const M2lChunk &c : f->m2l) biggest = std::max(biggest, c.count);
-    f->chunk_cap = biggest;
-    const int64_t S = (int64_t)P * (P + 1);
+    f->chunk_cap = 1;
+    f->scratch_reals = 1;
+    for (const M2lChunk &c : f->m2l) {
+        f->chunk_cap = std::max(f->chunk_cap, c.count);
+        f->scratch_reals = std::max(f->scratch_reals, c.count * f->Pl[c.level] * (f->Pl[c.level] + 1));
+    }
     auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t bM = up256(sizeof(double) * (size_t)(f->nbox * S));
+    const size_t bM = up256(sizeof(double) * (size_t)f->roff[levels + 1]);
     const size_t bI = up256(sizeof(int64_t) * (size_t)f->npairs);
     const size_t bR = up256(sizeof(double) * (size_t)(3 * f->npairs));
     const size_t bC = up256(sizeof(double) * centres.size());
@@ -259,7 +264,7 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
         delete f;
         return SH_EDEVICE;
     }
-    const size_t bX = up256(sizeof(double) * (size_t)(f->chunk_cap * S));
+    const size_t bX = up256(sizeof(double) * (size_t)f->scratch_reals);
     const size_t bT = up256(sizeof(int64_t) * (size_t)f->chunk_cap);
     const size_t bG = up256(sizeof(int64_t) * seg.size());
     if (hipMalloc(&f->mem, 2 * bM + 2 * bI + bR + bC + bN + bX + bT + bG) != hipSuccess) {
@@ -297,6 +302,18 @@ sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], 
     return SH_OK;
 }
 
+sh_status sh_fmm_create(sh_ctx *ctx, int P, int levels, const double origin[3], double width, int64_t npts,
+                        sh_fmm **out)
+{
+    if (levels < 2 || levels > SH_FMM_MAX_LEVELS) {
+        if (out) *out = nullptr;
+        return SH_EINVAL;
+    }
+    int orders[SH_FMM_MAX_LEVELS];
+    for (int l = 2; l <= levels; ++l) orders[l - 2] = P;
+    return sh_fmm_create_orders(ctx, levels, orders, origin, width, npts, out);
+}
+
 void sh_fmm_destroy(sh_fmm *f)
 {
     if (!f) return;
@@ -322,11 +339,12 @@ hipError_t status_to_hip(sh_status st) { return st == SH_OK ? hipSuccess : hipEr
 // computed, and L2P adds the far field last.
 hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, hipStream_t s, bool fork)
 {
-    const int P = f->P, Lv = f->levels;
-    const int64_t S = (int64_t)P * (P + 1);
+    const int Lv = f->levels, P = f->Pl[Lv];
+    const int64_t S = (int64_t)P * (P + 1);  // leaves
     const int64_t nleaf = boxes_at(Lv);
-    double *Mleaf = f->M + f->lvl_off[Lv] * S;
-    double *Lleaf = f->L + f->lvl_off[Lv] * S;
+    double *Mleaf = f->M + f->roff[Lv];
+    double *Lleaf = f->L + f->roff[Lv];
+    auto sz = [&](int l) { return (int64_t)f->Pl[l] * (f->Pl[l] + 1); };
     hipError_t e;
     hipStream_t near = s;
     if (fork) {
@@ -337,10 +355,10 @@ hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, h
     if ((e = shfmm::launch_p2p(nleaf, f->npts, pts, q, f->nbr, out, 0u, near)) != hipSuccess) return e;
     if ((e = shfmm::launch_p2m(P, nleaf, f->leaf_centres, f->npts, pts, q, Mleaf, S, s)) != hipSuccess) return e;
     auto run = [&](const FmmCall &c, unsigned flags, double *pool) {
-        return status_to_hip(shfmm::translate_device(f->ctx, c.op, SH_F64, P, P, c.count, f->r + 3 * c.off,
-                                                     f->src + c.off, pool + f->lvl_off[c.level_in] * S, S,
-                                                     f->dst + c.off, pool + f->lvl_off[c.level_out] * S, S, flags,
-                                                     s));
+        const int li = c.level_in, lo = c.level_out;
+        return status_to_hip(shfmm::translate_device(f->ctx, c.op, SH_F64, f->Pl[li], f->Pl[lo], c.count,
+                                                     f->r + 3 * c.off, f->src + c.off, pool + f->roff[li], sz(li),
+                                                     f->dst + c.off, pool + f->roff[lo], sz(lo), flags, s));
     };
     // upward pass: the first octant of a level overwrites its parents
     for (size_t i = 0; i < f->up.size(); ++i)
@@ -349,11 +367,11 @@ hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, h
     // into its local expansion (overwriting: every target of levels 2..L is in one chunk)
     for (const M2lChunk &c : f->m2l) {
         const int l = c.level;
-        if ((e = status_to_hip(shfmm::translate_device(f->ctx, SH_M2L, SH_F64, P, P, c.count, f->r + 3 * c.off,
-                                                       f->src + c.off, f->M + f->lvl_off[l] * S, S, f->iota,
-                                                       f->scratch, S, 0u, s))) != hipSuccess)
+        if ((e = status_to_hip(shfmm::translate_device(f->ctx, SH_M2L, SH_F64, f->Pl[l], f->Pl[l], c.count,
+                                                       f->r + 3 * c.off, f->src + c.off, f->M + f->roff[l], sz(l),
+                                                       f->iota, f->scratch, sz(l), 0u, s))) != hipSuccess)
             return e;
-        if ((e = shfmm::launch_seg_sum(f->L + f->lvl_off[l] * S, S, f->seg + f->seg_off[l], c.tb, c.te, c.off,
+        if ((e = shfmm::launch_seg_sum(f->L + f->roff[l], sz(l), f->seg + f->seg_off[l], c.tb, c.te, c.off,
                                        f->scratch, s)) != hipSuccess)
             return e;
     }

@@ -70,17 +70,19 @@ def _direct(pts, q, targets=None):
     return out
 
 
-def _oracle_fmm(orc, P, levels, origin, width, pts, q):
+def _oracle_fmm(orc, P, levels, origin, width, pts, q, orders=None):
     """The FMM from oracle primitives: P2M, M2M up, M2L over interaction lists, L2L down, L2P,
-    plus the direct near field over the 27 neighbouring leaves."""
+    plus the direct near field over the 27 neighbouring leaves.  orders[l - 2] is the order of
+    level l (default P everywhere); M2M and L2L translate between the two levels' orders."""
     nleaf, npts = q.shape
     th = 16
-    M = {levels: orc.p2m_batch(P, _centres(levels, origin, width), pts, q, nthreads=th)}
-    for lev in range(levels, 0, -1):
+    Pl = {lev: (orders[lev - 2] if orders else P) for lev in range(2, levels + 1)}
+    M = {levels: orc.p2m_batch(Pl[levels], _centres(levels, origin, width), pts, q, nthreads=th)}
+    for lev in range(levels, 2, -1):
         n, ijk = _grid(lev)
         parent = ((ijk[:, 0] // 2) * (n // 2) + ijk[:, 1] // 2) * (n // 2) + ijk[:, 2] // 2
         r = _centres(lev - 1, origin, width)[parent] - _centres(lev, origin, width)
-        moved = orc.translate_batch("m2m", P, P, r, M[lev], nthreads=th)
+        moved = orc.translate_batch("m2m", Pl[lev], Pl[lev - 1], r, M[lev], nthreads=th)
         M[lev - 1] = np.zeros((8 ** (lev - 1), moved.shape[1]))
         np.add.at(M[lev - 1], parent, moved)
     Lx = {}
@@ -97,15 +99,15 @@ def _oracle_fmm(orc, P, levels, origin, width, pts, q):
                 src.append(s)
                 dst.append(b)
         src, dst = np.array(src), np.array(dst)
-        out = orc.translate_batch("m2l", P, P, c[dst] - c[src], M[lev][src], nthreads=th)
+        out = orc.translate_batch("m2l", Pl[lev], Pl[lev], c[dst] - c[src], M[lev][src], nthreads=th)
         Lx[lev] = np.zeros((8 ** lev, out.shape[1]))
         np.add.at(Lx[lev], dst, out)
     for lev in range(2, levels):
         n, ijk = _grid(lev + 1)
         parent = ((ijk[:, 0] // 2) * (n // 2) + ijk[:, 1] // 2) * (n // 2) + ijk[:, 2] // 2
         r = _centres(lev + 1, origin, width) - _centres(lev, origin, width)[parent]
-        Lx[lev + 1] += orc.translate_batch("l2l", P, P, r, Lx[lev][parent], nthreads=th)
-    far = orc.l2p_batch(P, _centres(levels, origin, width), pts, Lx[levels], nthreads=th)
+        Lx[lev + 1] += orc.translate_batch("l2l", Pl[lev], Pl[lev + 1], r, Lx[lev][parent], nthreads=th)
+    far = orc.l2p_batch(Pl[levels], _centres(levels, origin, width), pts, Lx[levels], nthreads=th)
     n, ijk = _grid(levels)
     near = np.zeros_like(far)
     for b, (i, j, k) in enumerate(ijk):
@@ -120,9 +122,9 @@ def _oracle_fmm(orc, P, levels, origin, width, pts, q):
     return (far + near).reshape(-1, 4)
 
 
-def _gpu_fmm(ctx, P, levels, origin, width, pts, q, flags=0):
+def _gpu_fmm(ctx, P, levels, origin, width, pts, q, flags=0, orders=None):
     torch, dev = torch_dev()
-    f = sh.Fmm(ctx, P, levels, origin, width, q.shape[1])
+    f = sh.Fmm(ctx, P, levels, origin, width, q.shape[1], orders=orders)
     d_p = torch.from_numpy(np.ascontiguousarray(pts.reshape(-1, 3))).to(dev)
     d_q = torch.from_numpy(np.ascontiguousarray(q.reshape(-1))).to(dev)
     d_o = torch.full((q.size, 4), np.nan, dtype=torch.float64, device=dev)
@@ -149,6 +151,31 @@ def test_fmm_matches_oracle_composition(ctx, orc, P, levels, npts, flags):
     assert _rel(got[:, 0], ref[:, 0]) <= 1e-11
     assert _rel(got[:, 1:], ref[:, 1:]) <= 1e-11
     assert desc["leaves"] == 8 ** levels
+
+
+@pytest.mark.parametrize("orders", [(12, 8), (7, 10), (16, 5)], ids=["12-8", "7-10", "16-5"])
+def test_fmm_per_level_orders_match_oracle_composition(ctx, orc, orders):
+    """Per-level orders (levels 2..L): M2M and L2L between different orders, M2L within a
+    level, against the oracle composition with the same orders."""
+    levels = len(orders) + 1
+    npts = 4 if levels == 3 else 1
+    origin, width = (0.2, -0.4, 0.0), 1.5
+    print(f"[fmm] orders={orders}", flush=True)
+    pts, q = _particles(levels, npts, origin, width, seed=sum(orders))
+    got, desc = _gpu_fmm(ctx, 0, levels, origin, width, pts, q, orders=list(orders))
+    ref = _oracle_fmm(orc, 0, levels, origin, width, pts, q, orders=list(orders))
+    assert _rel(got[:, 0], ref[:, 0]) <= 1e-11
+    assert _rel(got[:, 1:], ref[:, 1:]) <= 1e-11
+
+
+def test_fmm_uniform_orders_equal_single_order(ctx):
+    """sh_fmm_create(P) and sh_fmm_create_orders with P at every level run the same FMM."""
+    levels, npts, P = 3, 5, 9
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=3)
+    a, _ = _gpu_fmm(ctx, P, levels, origin, width, pts, q)
+    b, _ = _gpu_fmm(ctx, 0, levels, origin, width, pts, q, orders=[P] * (levels - 1))
+    assert np.array_equal(a, b)
 
 
 def test_fmm_truncation_error_falls_with_order(ctx):
@@ -204,3 +231,5 @@ def test_fmm_rejects_bad_arguments(ctx):
         sh.Fmm(ctx, 10, 3, (0, 0, 0), 0.0, 8)  # empty cube
     with pytest.raises(sh.ShError):
         sh.Fmm(ctx, 33, 3, (0, 0, 0), 1.0, 8)  # order above the context's
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 0, 3, (0, 0, 0), 1.0, 8, orders=[10, 0])  # an order below 1
