@@ -8,16 +8,15 @@
 // by leaf.  All index and shift arrays are built once on the host at creation and kept on the
 // device; an evaluation only launches kernels.
 //
-// Launch grouping (each translation call needs distinct output solids when it accumulates):
-//   * M2M, level l -> l-1: one call per child octant (each parent has one child per octant);
-//     the first overwrites the parents, the other seven accumulate.
-//   * M2L at level l >= 2, target-major: the pairs (source b + d -> target b), d in
-//     [-3, 3]^3 \ [-1, 1]^3 with the parents of b and b + d neighbours (or equal), are listed
-//     target by target, so each target's pairs are contiguous.  One indexed launch per chunk
-//     of targets writes every translation to its own scratch solid, and a segmented sum adds
-//     each target's run into its local expansion: a few large launches per level instead of
-//     one small launch per offset (whose targets overlap across offsets).
-//   * L2L, level l -> l+1: one call per child octant, accumulating into the children.
+// Launch grouping (a translation call that accumulates needs distinct output solids):
+//   * M2M (level l -> l-1) and M2L (within level l >= 2) are target-major: the pairs of each
+//     target (its 8 children; its interaction list, the boxes b + d with d in
+//     [-3, 3]^3 \ [-1, 1]^3 whose parents neighbour b's parent) are listed target by target, so
+//     each target's pairs are contiguous.  One indexed launch per chunk of targets writes every
+//     translation to its own scratch solid, and a segmented sum adds each target's run into its
+//     expansion: a few large launches per level, not one small launch per offset or octant.
+//   * L2L (level l -> l+1): one call per level; every child is the target of exactly one L2L,
+//     which accumulates into the child's M2L result.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,11 +41,15 @@ struct FmmCall {
     int64_t off;  // first pair in the shared src / dst / r arrays
 };
 
-// M2L of the targets [tb, te) of one level: pairs [off, off + count) of the shared arrays.
-struct M2lChunk {
-    int level;
+// Target-major translations (M2M into parents, M2L within a level) for the targets
+// [tb, te) of level level_out: pairs [off, off + count) of the shared arrays; the targets'
+// pair offsets are seg[seg_base + t].
+struct Chunk {
+    int op;
+    int level_in, level_out;
     int64_t off, count;
     int64_t tb, te;
+    int64_t seg_base;
 };
 
 constexpr int64_t kScratchBytes = (int64_t)1 << 30;  // M2L scratch solids per chunk
@@ -61,9 +64,8 @@ struct sh_fmm {
     int64_t npts = 0;
     double origin[3] = {0, 0, 0};
     double width = 1;
-    std::vector<FmmCall> up, down;
-    std::vector<M2lChunk> m2l;
-    std::vector<int64_t> seg_off;  // level l's target offsets start at seg + seg_off[l]
+    std::vector<FmmCall> down;
+    std::vector<Chunk> up, m2l;
     int64_t chunk_cap = 0;         // iota entries: pairs of the largest chunk
     int64_t scratch_reals = 0;
     // device memory: one allocation
@@ -113,78 +115,77 @@ void build(sh_fmm *f, HostPlan &hp, std::vector<int64_t> &seg, std::vector<doubl
            std::vector<int32_t> &nbr)
 {
     const int Lv = f->levels;
-    // upward: children at level l (octant o) -> parents at level l - 1 >= 2 (the multipoles
-    // of levels 0 and 1 have no interaction list to feed)
+    // Appends the pairs of every target of level lo (add_pairs(t) lists target t's sources)
+    // and cuts them into chunks whose scratch solids fit in kScratchBytes.
+    auto chunks = [&](int op, int li, int lo, std::vector<Chunk> &outv, auto add_pairs) {
+        const int64_t S = (int64_t)f->Pl[lo] * (f->Pl[lo] + 1);
+        const int64_t cap = std::max<int64_t>(189, kScratchBytes / (S * (int64_t)sizeof(double)));
+        const int64_t base = (int64_t)seg.size();
+        Chunk ck{op, li, lo, (int64_t)hp.src.size(), 0, 0, 0, base};
+        const int64_t nt = boxes_at(lo);
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t first = (int64_t)hp.src.size();
+            seg.push_back(first);
+            add_pairs(t);
+            if ((int64_t)hp.src.size() - ck.off > cap) {  // close the chunk before target t
+                ck.count = first - ck.off;
+                ck.te = t;
+                outv.push_back(ck);
+                ck = Chunk{op, li, lo, first, 0, t, 0, base};
+            }
+        }
+        seg.push_back((int64_t)hp.src.size());
+        ck.count = (int64_t)hp.src.size() - ck.off;
+        ck.te = nt;
+        outv.push_back(ck);
+    };
+    // upward: the 8 children at level l of every parent at level l - 1 >= 2 (the multipoles of
+    // levels 0 and 1 have no interaction list to feed)
     for (int l = Lv; l >= 3; --l) {
         const int64_t n = (int64_t)1 << l, np = n / 2;
         const double w = f->width / (double)n;
-        for (int o = 0; o < 8; ++o) {
-            const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_M2M, l, l - 1, 0, (int64_t)hp.src.size()};
-            for (int64_t px = 0; px < np; ++px)
-                for (int64_t py = 0; py < np; ++py)
-                    for (int64_t pz = 0; pz < np; ++pz)
-                        hp.add(box_index(n, 2 * px + ox, 2 * py + oy, 2 * pz + oz), box_index(np, px, py, pz),
-                               (0.5 - ox) * w, (0.5 - oy) * w, (0.5 - oz) * w);
-            c.count = (int64_t)hp.src.size() - c.off;
-            f->up.push_back(c);
-        }
+        chunks(SH_M2M, l, l - 1, f->up, [&](int64_t pb) {
+            const int64_t px = pb / (np * np), py = (pb / np) % np, pz = pb % np;
+            for (int o = 0; o < 8; ++o) {
+                const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+                hp.add(box_index(n, 2 * px + ox, 2 * py + oy, 2 * pz + oz), pb, (0.5 - ox) * w, (0.5 - oy) * w,
+                       (0.5 - oz) * w);
+            }
+        });
     }
     // M2L at levels 2..L, target by target: offsets d with max |d_i| >= 2, parents neighbours
-    f->seg_off.assign(Lv + 1, 0);
     for (int l = 2; l <= Lv; ++l) {
-        const int64_t S = (int64_t)f->Pl[l] * (f->Pl[l] + 1);
-        const int64_t cap = std::max<int64_t>(189, kScratchBytes / (S * (int64_t)sizeof(double)));
         const int64_t n = (int64_t)1 << l;
         const double w = f->width / (double)n;
-        f->seg_off[l] = (int64_t)seg.size();
-        M2lChunk ck{l, (int64_t)hp.src.size(), 0, 0, 0};
-        for (int64_t ix = 0; ix < n; ++ix)
-            for (int64_t iy = 0; iy < n; ++iy)
-                for (int64_t iz = 0; iz < n; ++iz) {
-                    const int64_t b = box_index(n, ix, iy, iz);
-                    const int64_t first = (int64_t)hp.src.size();
-                    seg.push_back(first);
-                    for (int dx = -3; dx <= 3; ++dx)
-                        for (int dy = -3; dy <= 3; ++dy)
-                            for (int dz = -3; dz <= 3; ++dz) {
-                                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-                                const int64_t sx = ix + dx, sy = iy + dy, sz = iz + dz;
-                                if (sx < 0 || sy < 0 || sz < 0 || sx >= n || sy >= n || sz >= n) continue;
-                                if (std::abs(fdiv2(sx) - fdiv2(ix)) > 1 || std::abs(fdiv2(sy) - fdiv2(iy)) > 1 ||
-                                    std::abs(fdiv2(sz) - fdiv2(iz)) > 1)
-                                    continue;
-                                // r = x_B - x_A = centre(target) - centre(source) = -d w
-                                hp.add(box_index(n, sx, sy, sz), b, -dx * w, -dy * w, -dz * w);
-                            }
-                    // close the chunk before this target if its pairs would not fit
-                    if ((int64_t)hp.src.size() - ck.off > cap) {
-                        ck.count = first - ck.off;
-                        ck.te = b;
-                        f->m2l.push_back(ck);
-                        ck = M2lChunk{l, first, 0, b, 0};
+        chunks(SH_M2L, l, l, f->m2l, [&](int64_t b) {
+            const int64_t ix = b / (n * n), iy = (b / n) % n, iz = b % n;
+            for (int dx = -3; dx <= 3; ++dx)
+                for (int dy = -3; dy <= 3; ++dy)
+                    for (int dz = -3; dz <= 3; ++dz) {
+                        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+                        const int64_t sx = ix + dx, sy = iy + dy, sz = iz + dz;
+                        if (sx < 0 || sy < 0 || sz < 0 || sx >= n || sy >= n || sz >= n) continue;
+                        if (std::abs(fdiv2(sx) - fdiv2(ix)) > 1 || std::abs(fdiv2(sy) - fdiv2(iy)) > 1 ||
+                            std::abs(fdiv2(sz) - fdiv2(iz)) > 1)
+                            continue;
+                        // r = x_B - x_A = centre(target) - centre(source) = -d w
+                        hp.add(box_index(n, sx, sy, sz), b, -dx * w, -dy * w, -dz * w);
                     }
-                }
-        seg.push_back((int64_t)hp.src.size());
-        ck.count = (int64_t)hp.src.size() - ck.off;
-        ck.te = boxes_at(l);
-        f->m2l.push_back(ck);
+        });
     }
-    // downward: parents at level l -> children at level l + 1 (octant o), from level 2
+    // downward: every child at level l + 1 from its parent at level l >= 2, one call per level
+    // (each child is the target of exactly one L2L, so the call accumulates race-free)
     for (int l = 2; l < Lv; ++l) {
         const int64_t np = (int64_t)1 << l, n = 2 * np;
         const double w = f->width / (double)n;
-        for (int o = 0; o < 8; ++o) {
-            const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-            FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size()};
-            for (int64_t px = 0; px < np; ++px)
-                for (int64_t py = 0; py < np; ++py)
-                    for (int64_t pz = 0; pz < np; ++pz)
-                        hp.add(box_index(np, px, py, pz), box_index(n, 2 * px + ox, 2 * py + oy, 2 * pz + oz),
-                               (ox - 0.5) * w, (oy - 0.5) * w, (oz - 0.5) * w);
-            c.count = (int64_t)hp.src.size() - c.off;
-            f->down.push_back(c);
-        }
+        FmmCall c{SH_L2L, l, l + 1, 0, (int64_t)hp.src.size()};
+        for (int64_t cx = 0; cx < n; ++cx)
+            for (int64_t cy = 0; cy < n; ++cy)
+                for (int64_t cz = 0; cz < n; ++cz)
+                    hp.add(box_index(np, cx / 2, cy / 2, cz / 2), box_index(n, cx, cy, cz), ((cx & 1) - 0.5) * w,
+                           ((cy & 1) - 0.5) * w, ((cz & 1) - 0.5) * w);
+        c.count = (int64_t)hp.src.size() - c.off;
+        f->down.push_back(c);
     }
     // leaves: centres and the 27 neighbours (itself included), -1 outside the cube
     const int64_t n = (int64_t)1 << Lv;
@@ -249,10 +250,11 @@ sh_status sh_fmm_create_orders(sh_ctx *ctx, int levels, const int *orders, const
     // scratch for the largest chunk built (chunks were cut at kScratchBytes)
     f->chunk_cap = 1;
     f->scratch_reals = 1;
-    for (const M2lChunk &c : f->m2l) {
-        f->chunk_cap = std::max(f->chunk_cap, c.count);
-        f->scratch_reals = std::max(f->scratch_reals, c.count * f->Pl[c.level] * (f->Pl[c.level] + 1));
-    }
+    for (const std::vector<Chunk> *v : {&f->up, &f->m2l})
+        for (const Chunk &c : *v) {
+            f->chunk_cap = std::max(f->chunk_cap, c.count);
+            f->scratch_reals = std::max(f->scratch_reals, c.count * f->Pl[c.level_out] * (f->Pl[c.level_out] + 1));
+        }
     auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t bM = up256(sizeof(double) * (size_t)f->roff[levels + 1]);
     const size_t bI = up256(sizeof(int64_t) * (size_t)f->npairs);
@@ -360,21 +362,22 @@ hipError_t enqueue(sh_fmm *f, const double *pts, const double *q, double *out, h
                                                      f->r + 3 * c.off, f->src + c.off, pool + f->roff[li], sz(li),
                                                      f->dst + c.off, pool + f->roff[lo], sz(lo), flags, s));
     };
-    // upward pass: the first octant of a level overwrites its parents
-    for (size_t i = 0; i < f->up.size(); ++i)
-        if ((e = run(f->up[i], (i % 8 == 0) ? 0u : SH_ACCUMULATE, f->M)) != hipSuccess) return e;
-    // M2L: every translation of a chunk into its scratch solid, then each target's run summed
-    // into its local expansion (overwriting: every target of levels 2..L is in one chunk)
-    for (const M2lChunk &c : f->m2l) {
-        const int l = c.level;
-        if ((e = status_to_hip(shfmm::translate_device(f->ctx, SH_M2L, SH_F64, f->Pl[l], f->Pl[l], c.count,
-                                                       f->r + 3 * c.off, f->src + c.off, f->M + f->roff[l], sz(l),
-                                                       f->iota, f->scratch, sz(l), 0u, s))) != hipSuccess)
-            return e;
-        if ((e = shfmm::launch_seg_sum(f->L + f->roff[l], sz(l), f->seg + f->seg_off[l], c.tb, c.te, c.off,
-                                       f->scratch, s)) != hipSuccess)
-            return e;
-    }
+    // target-major steps: every translation of a chunk into its scratch solid, then each
+    // target's run summed into its expansion (overwriting: every target is in one chunk)
+    auto run_chunk = [&](const Chunk &c, const double *pool_in, double *pool_out) {
+        const int li = c.level_in, lo = c.level_out;
+        hipError_t e2 = status_to_hip(shfmm::translate_device(f->ctx, c.op, SH_F64, f->Pl[li], f->Pl[lo], c.count,
+                                                              f->r + 3 * c.off, f->src + c.off, pool_in + f->roff[li],
+                                                              sz(li), f->iota, f->scratch, sz(lo), 0u, s));
+        if (e2 != hipSuccess) return e2;
+        return shfmm::launch_seg_sum(pool_out + f->roff[lo], sz(lo), f->seg + c.seg_base, c.tb, c.te, c.off,
+                                     f->scratch, s);
+    };
+    // upward pass (parents summing their 8 children), then M2L at every level
+    for (const Chunk &c : f->up)
+        if ((e = run_chunk(c, f->M, f->M)) != hipSuccess) return e;
+    for (const Chunk &c : f->m2l)
+        if ((e = run_chunk(c, f->M, f->L)) != hipSuccess) return e;
     for (const FmmCall &c : f->down)
         if ((e = run(c, SH_ACCUMULATE, f->L)) != hipSuccess) return e;
     if (fork) {
@@ -444,8 +447,8 @@ sh_status sh_fmm_describe(const sh_fmm *f, int64_t *counts)
 {
     if (!f || !counts) return SH_EINVAL;
     int64_t t[3] = {0, 0, 0};
-    for (const FmmCall &c : f->up) t[0] += c.count;
-    for (const M2lChunk &c : f->m2l) t[1] += c.count;
+    for (const Chunk &c : f->up) t[0] += c.count;
+    for (const Chunk &c : f->m2l) t[1] += c.count;
     for (const FmmCall &c : f->down) t[2] += c.count;
     counts[0] = t[0];
     counts[1] = t[1];

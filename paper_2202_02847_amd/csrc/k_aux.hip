@@ -174,6 +174,84 @@ __global__ __launch_bounds__(64) void k_p2m(int P, int64_t count, const double *
     }
 }
 
+// P2M for orders up to 16, with the order PO known at compile time: the same lane split as
+// k_p2m, but each lane keeps the sums of its column m and the recurrence reciprocals
+// 1/(n^2 - m^2) in registers, so the per-point work is a register FMA chain instead of
+// dependent LDS read-modify-writes; the sums meet in LDS once per cluster.
+template <int PO>
+__global__ __launch_bounds__(64) void k_p2m_reg(int64_t count, const double *centres, int64_t npts,
+                                                const double *pts, const double *q, double *Mout, int64_t ldM)
+{
+    extern __shared__ double accm[];  // G copies of PO(PO+1)
+    constexpr int S = PO * (PO + 1);
+    constexpr int G = 64 / PO;
+    const int lane = threadIdx.x;
+    const int g = lane / PO, m = lane - g * PO;
+    const bool active = g < G;
+    double inv[PO];
+#pragma unroll
+    for (int n = 0; n < PO; ++n) inv[n] = (n > m) ? 1.0 / ((double)n * n - (double)m * m) : 0.0;
+    for (int64_t c = blockIdx.x; c < count; c += gridDim.x) {
+        double sr[PO], si[PO];
+#pragma unroll
+        for (int n = 0; n < PO; ++n) {
+            sr[n] = 0.0;
+            si[n] = 0.0;
+        }
+        const double cx = centres[3 * c], cy = centres[3 * c + 1], cz = centres[3 * c + 2];
+        for (int64_t j = active ? g : npts; j < npts; j += G) {
+            const double *pj = pts + 3 * (npts * c + j);
+            const double x = pj[0] - cx, y = pj[1] - cy, z = pj[2] - cz;
+            const double r2 = x * x + y * y + z * z;
+            const double qj = q[npts * c + j];
+            // R_m^m = prod_{i=1}^{m} (x+iy)/(2i)
+            double dr = 1.0, di = 0.0;
+            for (int i = 1; i <= m; ++i) {
+                const double f = 0.5 / (double)i;
+                const double nr = (x * dr - y * di) * f, ni = (x * di + y * dr) * f;
+                dr = nr;
+                di = ni;
+            }
+            // (n^2 - m^2) R_n^m = (2n-1) z R_{n-1}^m - |r|^2 R_{n-2}^m, n > m
+            double ar = dr, ai = di, br = 0.0, bi = 0.0;
+#pragma unroll
+            for (int n = 0; n < PO; ++n) {
+                if (n > m) {
+                    const double tz = (double)(2 * n - 1) * z;
+                    const double cr = (tz * ar - r2 * br) * inv[n], ci = (tz * ai - r2 * bi) * inv[n];
+                    br = ar;
+                    bi = ai;
+                    ar = cr;
+                    ai = ci;
+                }
+                if (n >= m) {
+                    sr[n] += qj * ar;
+                    si[n] += qj * ai;
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int n = 0; n < PO; ++n)
+                if (n >= m) {
+                    accm[g * S + solid_pos(n, m)] = sr[n];
+                    accm[g * S + solid_pos(n, m) + 1] = si[n];
+                }
+        }
+        __syncthreads();
+        double *Mo = Mout + c * ldM;
+        for (int i = lane; i < S; i += 64) {
+            int n = (int)((sqrtf(4.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+            while ((n + 1) * (n + 2) <= i) ++n;
+            while (n * (n + 1) > i) --n;
+            double v = 0.0;
+            for (int k = 0; k < G; ++k) v += accm[k * S + i];
+            Mo[i] = (i == n * (n + 1) + 1) ? 0.0 : v;
+        }
+        __syncthreads();
+    }
+}
+
 // L2P: one lane per target, the 64 lanes of a wavefront on targets of one box, so that the
 // box's local expansion is read through the scalar cache.  R_k^j(x - c) is generated
 // column by column (j) by the Appendix recurrences and used at once:
@@ -364,6 +442,31 @@ hipError_t launch_p2m(int P, int64_t count, const double *centres, int64_t npts,
     const int G = P <= 64 ? 64 / P : 1;
     const size_t smem = (size_t)G * P * (P + 1) * sizeof(double);
     const int64_t grid64 = count < (1 << 20) ? count : (1 << 20);
+    switch (P) {
+#define SH_P2M_REG(PO)                                                                                              \
+    case PO:                                                                                                        \
+        hipLaunchKernelGGL(k_p2m_reg<PO>, dim3((unsigned)grid64), dim3(64), smem, s, count, centres, npts, pts, q, M, \
+                           ldM);                                                                                    \
+        return hipGetLastError();
+        SH_P2M_REG(2)
+        SH_P2M_REG(3)
+        SH_P2M_REG(4)
+        SH_P2M_REG(5)
+        SH_P2M_REG(6)
+        SH_P2M_REG(7)
+        SH_P2M_REG(8)
+        SH_P2M_REG(9)
+        SH_P2M_REG(10)
+        SH_P2M_REG(11)
+        SH_P2M_REG(12)
+        SH_P2M_REG(13)
+        SH_P2M_REG(14)
+        SH_P2M_REG(15)
+        SH_P2M_REG(16)
+#undef SH_P2M_REG
+    default:
+        break;
+    }
     hipLaunchKernelGGL(k_p2m, dim3((unsigned)grid64), dim3(64), smem, s, P, count, centres, npts, pts, q, M, ldM);
     return hipGetLastError();
 }
