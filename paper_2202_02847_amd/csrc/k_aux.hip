@@ -347,6 +347,18 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
     }
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate (about 23 correct bits) refined by two
+// Newton-Raphson steps for the reciprocal square root, y <- y (3 - x y^2) / 2, each of which
+// roughly doubles the number of correct bits.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // P2P (the near field of eq. nbody with G = 1/|x - y|): one lane per target, the 64 lanes of a
 // wavefront on targets of one box; the sources of each neighbour box (nbr[27c + k], -1 for
 // none) are read by wave-uniform scalar loads.  Adds q_j / |x - y_j| and its gradient
@@ -375,7 +387,7 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t count, int64_t chunks, int6
             for (int64_t s = 0; s < npts; ++s) {
                 const double dx = x - P[3 * (s0 + s)], dy = y - P[3 * (s0 + s) + 1], dz = z - P[3 * (s0 + s) + 2];
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const double inv = (r2 > 0.0) ? 1.0 / sqrt(r2) : 0.0;
+                const double inv = (r2 > 0.0) ? rsqrt_nr(r2) : 0.0;
                 const double qi = Q[s0 + s] * inv;
                 const double qi3 = qi * inv * inv;
                 phi += qi;
