@@ -24,6 +24,7 @@ SH_F64, SH_F32 = 0, 1
 SH_ACCUMULATE = 1
 SH_SINGLE_HEIGHT = 2  # single-height M2L (p_in = p_out)
 SH_FMM_NO_GRAPH = 1
+SH_FMM_MAX_LEVELS = 6
 SH_PLAN_AUTOTUNE = 2
 SH_PLAN_NO_GRAPH = 4
 SH_SHARED_FP32 = 1

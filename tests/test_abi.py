@@ -26,6 +26,21 @@ def test_binding_mirrors_header_names():
         assert hasattr(sh, n), n
 
 
+def test_binding_constants_match_header():
+    """Every #define SH_* and enumerator value of the header equals the binding's constant."""
+    text = open(sh.HEADER).read()
+    found = {}
+    for name, val in re.findall(r"^#define (SH_[A-Z0-9_]+) (\d+)u?\b", text, re.M):
+        found[name] = int(val)
+    for name, val in re.findall(r"\b(SH_[A-Z0-9_]+) = (-?\d+)", text):
+        found[name] = int(val)
+    assert len(found) >= 20
+    missing = [n for n in found if not hasattr(sh, n)]
+    assert not missing, missing
+    wrong = {n: (v, getattr(sh, n)) for n, v in found.items() if getattr(sh, n) != v}
+    assert not wrong, wrong
+
+
 def test_strerror_texts():
     for code in (sh.SH_OK, sh.SH_EINVAL, sh.SH_EORDER, sh.SH_ESHIFT, sh.SH_ENOMEM, sh.SH_EDEVICE, sh.SH_EBUSY):
         assert sh.sh_strerror(code)
