@@ -380,8 +380,10 @@ sh_status sh_l2p_batch_f64(const sh_ctx *ctx, int P, int64_t count, const double
  * exactly `npts` particles, stored leaf by leaf (particle j of leaf b at pts[3(npts b + j)]).
  * Particles must lie in their leaf's cube (the expansions converge only then).  FP64.
  * Every index and shift array is built and uploaded at creation; the handle owns its device
- * memory (multipole and local pools of every level, the call lists).  Handles are not
- * thread-safe: one evaluation at a time per handle. */
+ * memory (multipole and local pools of every level, M2M/M2L scratch, the call lists).  Calls on
+ * one handle are serialised on the host, but its evaluations share those pools on the device:
+ * evaluations issued on different streams must not overlap in time, and the caller
+ * synchronises the stream of the last evaluation before sh_fmm_destroy. */
 #define SH_FMM_MAX_LEVELS 6
 typedef struct sh_fmm sh_fmm;
 
