@@ -6,6 +6,8 @@
 //   * L2P: the potential of a local expansion (eq. MLexpansions) and its gradient at
 //     target points;
 //   * P2P: the direct near-field sum over neighbouring boxes (eq. nbody).
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "near_field.hpp"
 
@@ -262,10 +264,15 @@ __global__ __launch_bounds__(64) void k_p2m_reg(int64_t count, const double *cen
 // d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1}) / 2, d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1}) / 2)
 // gathered per R_k^j instead of per L_n^m.  The term of -j equals the conjugate of that of
 // j, so columns j > 0 count twice.  Im L_n^0 is ignored (read as 0).
-__global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunks, const double *centres,
+// MB (boxes of at most 32 targets): a wavefront takes bpw = 64 / npts whole boxes, lane
+// (kb, j) target j of box kb, and reads each lane's box data by vector loads (the lanes of one
+// box share its cache lines); otherwise the wavefront covers 64 targets of one box.
+template <bool MB>
+__global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunks, int64_t bpw, const double *centres,
                                              int64_t npts, const double *pts, const double *Lpool,
                                              int64_t ldL, double *out, unsigned flags)
 {
+    using RP = std::conditional_t<MB, const double *, lpt_cptr>;
     // recurrence constants, shared by the workgroup: rc[k P + j] = 1/(k^2 - j^2) (k > j),
     // rc[j P + j] = 1/(2j) (j > 0)
     extern __shared__ double rc[];
@@ -276,15 +283,25 @@ __global__ __launch_bounds__(256) void k_l2p(int P, int64_t count, int64_t chunk
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t ntask = count * chunks;
+    const int64_t ntask = MB ? (count + bpw - 1) / bpw : count * chunks;
     const bool acc = (flags & 1u) != 0;
     for (int64_t task = (int64_t)blockIdx.x * 4 + wave; task < ntask; task += (int64_t)gridDim.x * 4) {
-        const int64_t c = task / chunks;
-        const int64_t j0 = (task - c * chunks) * 64 + lane;
-        const bool act = j0 < npts;
+        int64_t c, j0;
+        bool act;
+        if constexpr (MB) {
+            const int64_t kb = lane / npts;
+            c = task * bpw + kb;
+            j0 = lane - kb * npts;
+            act = kb < bpw && c < count;
+            if (!act) c = 0;  // idle lanes read box 0
+        } else {
+            c = task / chunks;
+            j0 = (task - c * chunks) * 64 + lane;
+            act = j0 < npts;
+        }
         const int64_t t = c * npts + (act ? j0 : 0);
-        const lpt_cptr Lc = (lpt_cptr)(Lpool + c * ldL);
-        const lpt_cptr cc = (lpt_cptr)(centres + 3 * c);
+        const RP Lc = (RP)(Lpool + c * ldL);
+        const RP cc = (RP)(centres + 3 * c);
         const double x = pts[3 * t] - cc[0], y = pts[3 * t + 1] - cc[1], z = pts[3 * t + 2] - cc[2];
         const double r2 = x * x + y * y + z * z;
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
@@ -363,20 +380,35 @@ __device__ __forceinline__ double rsqrt_nr(double x)
 // wavefront on targets of one box; the sources of each neighbour box (nbr[27c + k], -1 for
 // none) are read by wave-uniform scalar loads.  Adds q_j / |x - y_j| and its gradient
 // -q_j (x - y_j) / |x - y_j|^3 over sources at a distance > 0 (a target does not see itself).
-__global__ __launch_bounds__(256) void k_p2p(int64_t count, int64_t chunks, int64_t npts, const double *pts,
-                                             const double *q, const int32_t *nbr, double *out, unsigned flags)
+// MB: several whole boxes per wavefront, as in k_l2p.
+template <bool MB>
+__global__ __launch_bounds__(256) void k_p2p(int64_t count, int64_t chunks, int64_t bpw, int64_t npts,
+                                             const double *pts, const double *q, const int32_t *nbr, double *out,
+                                             unsigned flags)
 {
+    using RP = std::conditional_t<MB, const double *, lpt_cptr>;
+    using IP = std::conditional_t<MB, const int32_t *, const __attribute__((address_space(4))) int32_t *>;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t ntask = count * chunks;
+    const int64_t ntask = MB ? (count + bpw - 1) / bpw : count * chunks;
     const bool acc = (flags & 1u) != 0;
-    const lpt_cptr P = (lpt_cptr)pts;
-    const lpt_cptr Q = (lpt_cptr)q;
-    const __attribute__((address_space(4))) int32_t *NB = (const __attribute__((address_space(4))) int32_t *)nbr;
+    const RP P = (RP)pts;
+    const RP Q = (RP)q;
+    const IP NB = (IP)nbr;
     for (int64_t task = (int64_t)blockIdx.x * 4 + wave; task < ntask; task += (int64_t)gridDim.x * 4) {
-        const int64_t c = task / chunks;
-        const int64_t j0 = (task - c * chunks) * 64 + lane;
-        const bool act = j0 < npts;
+        int64_t c, j0;
+        bool act;
+        if constexpr (MB) {
+            const int64_t kb = lane / npts;
+            c = task * bpw + kb;
+            j0 = lane - kb * npts;
+            act = kb < bpw && c < count;
+            if (!act) c = 0;  // idle lanes read box 0
+        } else {
+            c = task / chunks;
+            j0 = (task - c * chunks) * 64 + lane;
+            act = j0 < npts;
+        }
         const int64_t t = c * npts + (act ? j0 : 0);
         const double x = pts[3 * t], y = pts[3 * t + 1], z = pts[3 * t + 2];
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
@@ -487,11 +519,20 @@ hipError_t launch_l2p(int P, int64_t count, const double *centres, int64_t npts,
                       const double *L, int64_t ldL, double *out, unsigned flags, hipStream_t s)
 {
     if (count <= 0 || npts <= 0) return hipSuccess;
+    const size_t smem = (size_t)P * P * sizeof(double);
+    if (npts <= 32) {
+        const int64_t bpw = 64 / npts;
+        const int64_t blocks = ((count + bpw - 1) / bpw + 3) / 4;
+        const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
+        hipLaunchKernelGGL(k_l2p<true>, dim3((unsigned)grid64), dim3(256), smem, s, P, count, (int64_t)1, bpw, centres,
+                           npts, pts, L, ldL, out, flags);
+        return hipGetLastError();
+    }
     const int64_t chunks = (npts + 63) / 64;
     const int64_t blocks = (count * chunks + 3) / 4;
     const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
-    hipLaunchKernelGGL(k_l2p, dim3((unsigned)grid64), dim3(256), (size_t)P * P * sizeof(double), s, P, count, chunks,
-                       centres, npts, pts, L, ldL, out, flags);
+    hipLaunchKernelGGL(k_l2p<false>, dim3((unsigned)grid64), dim3(256), smem, s, P, count, chunks, (int64_t)1, centres,
+                       npts, pts, L, ldL, out, flags);
     return hipGetLastError();
 }
 
@@ -499,10 +540,19 @@ hipError_t launch_p2p(int64_t count, int64_t npts, const double *pts, const doub
                       double *out, unsigned flags, hipStream_t s)
 {
     if (count <= 0 || npts <= 0) return hipSuccess;
+    if (npts <= 32) {
+        const int64_t bpw = 64 / npts;
+        const int64_t blocks = ((count + bpw - 1) / bpw + 3) / 4;
+        const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
+        hipLaunchKernelGGL(k_p2p<true>, dim3((unsigned)grid64), dim3(256), 0, s, count, (int64_t)1, bpw, npts, pts, q,
+                           nbr, out, flags);
+        return hipGetLastError();
+    }
     const int64_t chunks = (npts + 63) / 64;
     const int64_t blocks = (count * chunks + 3) / 4;
     const int64_t grid64 = blocks < (1 << 16) ? blocks : (1 << 16);
-    hipLaunchKernelGGL(k_p2p, dim3((unsigned)grid64), dim3(256), 0, s, count, chunks, npts, pts, q, nbr, out, flags);
+    hipLaunchKernelGGL(k_p2p<false>, dim3((unsigned)grid64), dim3(256), 0, s, count, chunks, (int64_t)1, npts, pts, q,
+                       nbr, out, flags);
     return hipGetLastError();
 }
 

@@ -73,9 +73,10 @@ def _err(got, ref):
     return float(np.max(np.max(np.abs(got - ref), axis=-1) / scale))
 
 
-# targets per box: one lane, a ragged wavefront, exactly one, several with a ragged tail
+# targets per box: several boxes per wavefront (<= 32: 5, 20 with a count that is not a multiple
+# of the 3 boxes per wavefront, exactly 32, one), one box per wavefront (33, 64, 70, 129, 200)
 @pytest.mark.parametrize("P,count,npts", [(1, 7, 5), (2, 9, 64), (10, 23, 70), (10, 5, 200), (16, 11, 33),
-                                          (24, 4, 129), (30, 3, 64), (31, 2, 1)])
+                                          (24, 4, 129), (30, 3, 64), (31, 2, 1), (12, 10, 20), (8, 5, 32)])
 def test_l2p_matches_oracle(ctx, orc, P, count, npts):
     centres, tgt, L, ref = _case(orc, P, count, npts, seed=100 + P * 7 + npts)
     got = _run(ctx, P, centres, tgt, L)
