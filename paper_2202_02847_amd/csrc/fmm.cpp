@@ -223,7 +223,7 @@ sh_status sh_fmm_create_orders(sh_ctx *ctx, int levels, const int *orders, const
         return SH_EINVAL;
     for (int l = 2; l <= levels; ++l)
         if (orders[l - 2] < 1 || orders[l - 2] > ctx->max_order) return SH_EORDER;
-    if (boxes_at(levels) * npts > ((int64_t)1 << 31)) return SH_EINVAL;
+    if (npts > ((int64_t)1 << 31) / boxes_at(levels)) return SH_EINVAL;  // at most 2^31 particles
     sh_fmm *f = new (std::nothrow) sh_fmm;
     if (!f) return SH_ENOMEM;
     f->ctx = ctx;

@@ -233,3 +233,5 @@ def test_fmm_rejects_bad_arguments(ctx):
         sh.Fmm(ctx, 33, 3, (0, 0, 0), 1.0, 8)  # order above the context's
     with pytest.raises(sh.ShError):
         sh.Fmm(ctx, 0, 3, (0, 0, 0), 1.0, 8, orders=[10, 0])  # an order below 1
+    with pytest.raises(sh.ShError):
+        sh.Fmm(ctx, 10, 3, (0, 0, 0), 1.0, 1 << 62)  # more than 2^31 particles (no overflow)
