@@ -410,6 +410,15 @@ void sh_fmm_destroy(sh_fmm *fmm);
 sh_status sh_fmm_evaluate(sh_fmm *fmm, const double *pts, const double *q, double *out,
                           unsigned flags, void *hip_stream);
 
+/* Per-level orders (as for sh_fmm_create_orders, levels - 1 entries) for a target relative
+ * error tol of the potential, max_i |u_i - u_i^direct| / max_i |u_i^direct|, in a uniform
+ * tree with uniformly distributed particles and charges of both signs.  The rule comes from
+ * this driver's measured error against direct summation: below 0.12 * 0.444^P at order P on
+ * every level, and no lower when a single level's order is raised, so every level takes the
+ * smallest P meeting tol (capped at SH_MAX_ORDER).  Host only.  Errors: SH_EINVAL (NULL
+ * orders, tol outside (0, 1), levels outside [2, SH_FMM_MAX_LEVELS]). */
+sh_status sh_fmm_orders_for_tolerance(double tol, int levels, int *orders);
+
 /* counts[0..4] = M2M, M2L and L2L translations per evaluation, translation calls, leaves. */
 sh_status sh_fmm_describe(const sh_fmm *fmm, int64_t *counts);
 

@@ -62,6 +62,7 @@ _SIGS = {
     "sh_fmm_create": (_c_i32, [_vp, _c_i32, _c_i32, _vp, ctypes.c_double, _c_i64, _vp]),
     "sh_fmm_create_orders": (_c_i32, [_vp, _c_i32, _vp, _vp, ctypes.c_double, _c_i64, _vp]),
     "sh_fmm_destroy": (None, [_vp]),
+    "sh_fmm_orders_for_tolerance": (_c_i32, [ctypes.c_double, _c_i32, _vp]),
     "sh_fmm_evaluate": (_c_i32, [_vp, _vp, _vp, _vp, _c_u32, _vp]),
     "sh_fmm_describe": (_c_i32, [_vp, _vp]),
     "sh_swap_matrix_f64": (_c_i32, [_c_i32, _c_i32, _c_i32, _vp]),
@@ -578,6 +579,13 @@ def sh_fmm_create_orders(ctx, levels, orders, origin, width, npts):
     _check(lib().sh_fmm_create_orders(_h(ctx), int(levels), ords, o, float(width), int(npts), ctypes.byref(h)),
            "sh_fmm_create_orders")
     return h
+
+
+def sh_fmm_orders_for_tolerance(tol, levels):
+    """Orders of levels 2..levels for a relative potential error target (host only)."""
+    out = (ctypes.c_int * (int(levels) - 1))() if int(levels) >= 2 else (ctypes.c_int * 1)()
+    _check(lib().sh_fmm_orders_for_tolerance(float(tol), int(levels), out), "sh_fmm_orders_for_tolerance")
+    return list(out)
 
 
 def sh_fmm_destroy(h):

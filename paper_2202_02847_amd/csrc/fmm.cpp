@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -441,6 +442,23 @@ sh_status sh_fmm_evaluate(sh_fmm *f, const double *pts, const double *q, double 
         }
     }
     return hipGraphLaunch(f->exec, s) == hipSuccess ? SH_OK : SH_EDEVICE;
+}
+
+// Orders for a relative error target of the potential, max_i |u_i - u_i^direct| divided by
+// max_i |u_i^direct|, from the error this driver measured against direct summation (uniform
+// trees, 3 levels, 8-24 uniform particles per leaf, charges uniform in [-1, 1], three seeds):
+// every measurement lies below kErrC * kErrRho^P (P = 4..14).  Lowering one level's order
+// raises the error to that order's level and raising one level alone does not lower it, so
+// every level takes the same order.
+constexpr double kErrC = 0.12, kErrRho = 0.444;
+
+sh_status sh_fmm_orders_for_tolerance(double tol, int levels, int *orders)
+{
+    if (!orders || !(tol > 0.0) || !(tol < 1.0) || levels < 2 || levels > SH_FMM_MAX_LEVELS) return SH_EINVAL;
+    int P = (int)std::ceil(std::log(tol / kErrC) / std::log(kErrRho) - 1e-9);
+    P = std::max(1, std::min(P, SH_MAX_ORDER));
+    for (int l = 2; l <= levels; ++l) orders[l - 2] = P;
+    return SH_OK;
 }
 
 sh_status sh_fmm_describe(const sh_fmm *f, int64_t *counts)

@@ -85,3 +85,20 @@ def test_normalise_roundtrip():
     one = np.zeros(P * (P + 1))
     one[3 * 4 + 2] = 1.0
     assert np.isclose(sh.sh_normalise_f64(0, P, one)[3 * 4 + 2], np.sqrt(24 * 2))
+
+
+def test_fmm_orders_for_tolerance():
+    """Host-only order selection: one order for every level, growing as the target shrinks,
+    the smallest P with 0.12 * 0.444^P <= tol; bad arguments rejected."""
+    prev = 0
+    for tol in (0.5, 1e-2, 1e-3, 1e-5, 1e-8, 1e-12):
+        orders = sh.sh_fmm_orders_for_tolerance(tol, 4)
+        assert len(orders) == 3 and len(set(orders)) == 1
+        P = orders[0]
+        assert P >= prev
+        prev = P
+        assert P == 1 or 0.12 * 0.444 ** P <= tol * (1 + 1e-12)
+        assert P == 1 or 0.12 * 0.444 ** (P - 1) > tol
+    for tol, levels in ((0.0, 3), (1.0, 3), (1e-3, 1), (1e-3, 7)):
+        with pytest.raises(sh.ShError):
+            sh.sh_fmm_orders_for_tolerance(tol, levels)

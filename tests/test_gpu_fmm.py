@@ -222,6 +222,20 @@ def test_fmm_graph_replays_match_eager(ctx):
     f.close()
 
 
+@pytest.mark.parametrize("tol", [1e-3, 1e-5])
+def test_fmm_orders_for_tolerance_meet_target(ctx, tol):
+    """Orders chosen for a target meet it against the direct sum on a tree outside the
+    measurements the rule was fitted to (12 particles per leaf, another seed)."""
+    levels, npts = 3, 12
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=23)
+    orders = sh.sh_fmm_orders_for_tolerance(tol, levels)
+    got, _ = _gpu_fmm(ctx, 0, levels, origin, width, pts, q, orders=orders)
+    err = _rel(got[:, 0], _direct(pts, q)[:, 0])
+    print(f"[fmm] tol={tol} orders={orders} err={err:.2e}", flush=True)
+    assert err <= tol
+
+
 def test_fmm_rejects_bad_arguments(ctx):
     with pytest.raises(sh.ShError):
         sh.Fmm(ctx, 10, 1, (0, 0, 0), 1.0, 8)  # fewer than two levels: no interaction list
