@@ -413,7 +413,7 @@ sh_status sh_fmm_evaluate(sh_fmm *fmm, const double *pts, const double *q, doubl
 /* Per-level orders (as for sh_fmm_create_orders, levels - 1 entries) for a target relative
  * error tol of the potential, max_i |u_i - u_i^direct| / max_i |u_i^direct|, in a uniform
  * tree with uniformly distributed particles and charges of both signs.  The rule comes from
- * this driver's measured error against direct summation: below 0.12 * 0.444^P at order P on
+ * this driver's measured error against direct summation: below 0.15 * 0.444^P at order P on
  * every level, and no lower when a single level's order is raised, so every level takes the
  * smallest P meeting tol (capped at SH_MAX_ORDER).  Host only.  Errors: SH_EINVAL (NULL
  * orders, tol outside (0, 1), levels outside [2, SH_FMM_MAX_LEVELS]). */

@@ -446,11 +446,11 @@ sh_status sh_fmm_evaluate(sh_fmm *f, const double *pts, const double *q, double 
 
 // Orders for a relative error target of the potential, max_i |u_i - u_i^direct| divided by
 // max_i |u_i^direct|, from the error this driver measured against direct summation (uniform
-// trees, 3 levels, 8-24 uniform particles per leaf, charges uniform in [-1, 1], three seeds):
+// trees, 3 levels, 8-24 uniform particles per leaf, charges uniform in [-1, 1], four seeds):
 // every measurement lies below kErrC * kErrRho^P (P = 4..14).  Lowering one level's order
 // raises the error to that order's level and raising one level alone does not lower it, so
 // every level takes the same order.
-constexpr double kErrC = 0.12, kErrRho = 0.444;
+constexpr double kErrC = 0.15, kErrRho = 0.444;
 
 sh_status sh_fmm_orders_for_tolerance(double tol, int levels, int *orders)
 {

@@ -89,7 +89,7 @@ def test_normalise_roundtrip():
 
 def test_fmm_orders_for_tolerance():
     """Host-only order selection: one order for every level, growing as the target shrinks,
-    the smallest P with 0.12 * 0.444^P <= tol; bad arguments rejected."""
+    the smallest P with 0.15 * 0.444^P <= tol; bad arguments rejected."""
     prev = 0
     for tol in (0.5, 1e-2, 1e-3, 1e-5, 1e-8, 1e-12):
         orders = sh.sh_fmm_orders_for_tolerance(tol, 4)
@@ -97,8 +97,8 @@ def test_fmm_orders_for_tolerance():
         P = orders[0]
         assert P >= prev
         prev = P
-        assert P == 1 or 0.12 * 0.444 ** P <= tol * (1 + 1e-12)
-        assert P == 1 or 0.12 * 0.444 ** (P - 1) > tol
+        assert P == 1 or 0.15 * 0.444 ** P <= tol * (1 + 1e-12)
+        assert P == 1 or 0.15 * 0.444 ** (P - 1) > tol
     for tol, levels in ((0.0, 3), (1.0, 3), (1e-3, 1), (1e-3, 7)):
         with pytest.raises(sh.ShError):
             sh.sh_fmm_orders_for_tolerance(tol, levels)
