@@ -374,21 +374,78 @@ def cpu_baseline(seconds_target=10.0):
             "per_core": n / dt / threads, "by_order": by_order}
 
 
-def run_counters(sh, ctx, torch, dev, P, steps):
-    """A short program for hardware-counter runs: a plain copy of 2^27 doubles (1 GiB read,
-    1 GiB written) and `steps` octree M2L launches at order P."""
+def run_counters(sh, ctx, torch, dev, what, steps):
+    """A short program for hardware-counter and kernel-trace runs: a plain copy of 2^27
+    doubles (1 GiB read, 1 GiB written; the reference for FETCH_SIZE/WRITE_SIZE scaling),
+    then `steps` launches of one workload and nothing else.
+
+    what: "P" or "m2l:P"  octree M2L at order P, FP64 (2^20 translations, 2^18 above P=16)
+          "m2l32:P"       the same in the FP32 normalised basis
+          "shared6:P" / "shared3:P" / "sharedf32:P"
+                          the shared-direction operator (BF16x6 / BF16x3 / FP32 MFMA) over
+                          2^20 translations in the 316 octree classes
+          "mixed64" / "mixed32"
+                          the 500,000-item mixed-order list through one tuned plan
+          "fmm"           the uniform-octree FMM, 262,144 particles at P=10"""
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    n = 1 << 20 if P <= 16 else 1 << 18
-    I = make_octree_inputs(sh, ctx, torch, dev, P, n)
-    d_out = torch.empty((n, solid(P)), dtype=torch.float64, device=dev)
-    for _ in range(max(1, steps)):
-        sh.sh_m2l_batch_f64(ctx, P, P, n, I["r"], I["M"], solid(P), d_out, solid(P))
+    torch.cuda.empty_cache()
+    kind, _, arg = what.partition(":")
+    if kind.isdigit():
+        kind, arg = "m2l", kind
+    steps = max(1, steps)
+    if kind in ("m2l", "m2l32"):
+        P = int(arg)
+        n = 1 << 20 if P <= 16 else 1 << 18
+        I = make_octree_inputs(sh, ctx, torch, dev, P, n)
+        if kind == "m2l":
+            d_in, d_r = I["M"], I["r"]
+            d_out = torch.empty((n, solid(P)), dtype=torch.float64, device=dev)
+            fn = sh.sh_m2l_batch_f64
+        else:
+            d_in = (I["M"] * norm_weights(sh, torch, dev, P, 0)).float()
+            d_r = I["r"].float()
+            d_out = torch.empty((n, solid(P)), dtype=torch.float32, device=dev)
+            fn = sh.sh_m2l_batch_f32
+        for _ in range(steps):
+            fn(ctx, P, P, n, d_r, d_in, solid(P), d_out, solid(P))
+    elif kind.startswith("shared"):
+        from paper_2202_02847_amd import workloads as wl
+
+        P = int(arg or 16)
+        prec = {"shared6": sh.SH_SHARED_BF16X6, "shared3": sh.SH_SHARED_BF16X3,
+                "sharedf32": sh.SH_SHARED_FP32}[kind]
+        n = 1 << 20
+        S = solid(P)
+        c = wl.config2(n_m2l=n, n_child=8, npts=32, P=P, seed_config=3)
+        order = np.argsort(c["dir_idx"], kind="stable")
+        counts = np.bincount(c["dir_idx"], minlength=len(wl.octree_offsets()))
+        d_pts = torch.from_numpy(np.ascontiguousarray(c["pts"][order])).to(dev)
+        d_q = torch.from_numpy(np.ascontiguousarray(c["q"][order])).to(dev)
+        del c
+        d_M = torch.empty((n, S), dtype=torch.float64, device=dev)
+        sh.sh_p2m_batch_f64(ctx, P, n, torch.zeros((n, 3), dtype=torch.float64, device=dev), d_pts.shape[1],
+                            d_pts, d_q, d_M, S)
+        d_M32 = (d_M * norm_weights(sh, torch, dev, P, 0)).float()
+        del d_M, d_pts, d_q
+        d_cs = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).to(dev)
+        d_L32 = torch.empty((n, S), dtype=torch.float32, device=dev)
+        op = sh.Shared(ctx, "m2l", P, P, wl.octree_offsets(), prec)
+        for _ in range(steps):
+            op.execute(n, d_cs, d_M32, S, d_L32, S)
+        torch.cuda.synchronize()
+        op.close()
+    elif kind in ("mixed64", "mixed32"):
+        run_mixed(sh, ctx, torch, dev, sh.SH_F64 if kind == "mixed64" else sh.SH_F32, reps=steps)
+    elif kind == "fmm":
+        run_fmm(sh, ctx, torch, dev, reps=steps)
+    else:
+        raise SystemExit(f"unknown counter workload {what!r}")
     torch.cuda.synchronize()
-    log(f"[counters] done: copy 1 GiB + {max(1, steps)} x M2L P={P} n={n}")
+    log(f"[counters] done: copy 1 GiB + {steps} x {what}")
 
 
 def main():
@@ -401,10 +458,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=50.0,
                     help="length of the serving workload's Poisson stream (200 jobs/s)")
-    ap.add_argument("--counters", type=int, default=0, metavar="P",
-                    help="counter-collection mode: one 1 GiB copy (the reference kernel for "
-                         "FETCH_SIZE/WRITE_SIZE scaling), then --steps launches of the octree M2L "
-                         "at order P (FP64), nothing else; prints no JSON line")
+    ap.add_argument("--counters", default="", metavar="WHAT",
+                    help="counter/trace mode: one 1 GiB copy (the reference kernel for "
+                         "FETCH_SIZE/WRITE_SIZE scaling), then --steps launches of one workload "
+                         "(P or m2l:P, m2l32:P, shared6:P, shared3:P, sharedf32:P, mixed64, mixed32, "
+                         "fmm), nothing else; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",

@@ -500,6 +500,71 @@ def pin_l2p_vs_direct_field(o):
     return worst, 1e-8
 
 
+# ---------------------------------------------------------------- batched entry points
+def _strided(o, rows, ld, fill):
+    a = np.full((rows, ld), fill, dtype=o.dtype)
+    return a, a.ctypes.data_as(o._P)
+
+
+def pin_batch_entry_points(o):
+    """The batched forms (every op, mixed orders, padded strides, several threads) equal the
+    single calls item by item, bit for bit, and write nothing past each output row.
+
+    The single calls are pinned above against closed forms and the direct sum; this pin
+    ties the batched dispatch, the op codes and the ld_in / ld_out strides to them.
+    Input padding holds NaN, so a read through the wrong stride shows in the result."""
+    rng = _rng(77)
+    worst = 0.0
+    single = {"m2m": o.m2m, "m2l": o.m2l, "l2l": o.l2l}
+    count, sentinel = 23, 7.25
+    for op, code in (("m2m", 0), ("m2l", 1), ("l2l", 2)):
+        for p_in, p_out in ((7, 7), (5, 9), (9, 4)):
+            ld_in, ld_out = size(p_in) + 5, size(p_out) + 3
+            C, Cp = _strided(o, count, ld_in, np.nan)
+            for i in range(count):
+                C[i, : size(p_in)] = _random_solid(rng, p_in)
+            lo, hi = (2.0, 4.0) if op == "m2l" else (0.25, 0.6)
+            r = np.array([_unit(rng) * rng.uniform(lo, hi) for _ in range(count)], dtype=o.dtype)
+            out, outp = _strided(o, count, ld_out, sentinel)
+            o._lib.or_translate_batch(code, count, p_in, p_out, r.ctypes.data_as(o._P), Cp, ld_in, outp, ld_out, 3)
+            for i in range(count):
+                want = single[op](p_in, p_out, r[i], C[i, : size(p_in)])
+                got = out[i, : size(p_out)]
+                if not np.array_equal(got, want) or not np.all(out[i, size(p_out):] == sentinel):
+                    worst = max(worst, _rel(got, want) if np.all(np.isfinite(got)) else np.inf, 1.0)
+    # P2M / P2L: cluster c reads its points at pts + 3*npts*c and writes row c of stride ldM
+    P, npts = 6, 5
+    centres = rng.uniform(-1, 1, (count, 3)).astype(o.dtype)
+    pts = (centres[:, None, :] + rng.uniform(-0.5, 0.5, (count, npts, 3))).astype(o.dtype)
+    q = rng.uniform(-1, 1, (count, npts)).astype(o.dtype)
+    for fn, one in ((o._lib.or_p2m_batch, o.p2m), (o._lib.or_p2l_batch, None)):
+        out, outp = _strided(o, count, size(P) + 4, sentinel)
+        far = centres if one is not None else centres + 3.0
+        fn(count, P, np.ascontiguousarray(far).ctypes.data_as(o._P), npts, pts.ctypes.data_as(o._P),
+           q.ctypes.data_as(o._P), outp, size(P) + 4, 2)
+        for c in range(count):
+            want = (one or o.p2l)(P, far[c], pts[c], q[c])
+            if not np.array_equal(out[c, : size(P)], want) or not np.all(out[c, size(P):] == sentinel):
+                worst = max(worst, 1.0)
+    # single-height M2L batch and L2P batch
+    Ms, Msp = _strided(o, count, size(P) + 2, np.nan)
+    for i in range(count):
+        Ms[i, : size(P)] = _random_solid(rng, P)
+    r = np.array([_unit(rng) * rng.uniform(2, 4) for _ in range(count)], dtype=o.dtype)
+    out, outp = _strided(o, count, size(P) + 1, sentinel)
+    o._lib.or_m2l_single_batch(count, P, r.ctypes.data_as(o._P), Msp, size(P) + 2, outp, size(P) + 1, 2)
+    for i in range(count):
+        want = o.m2l_single(P, r[i], Ms[i, : size(P)])
+        if not np.array_equal(out[i, : size(P)], want) or out[i, size(P)] != sentinel:
+            worst = max(worst, 1.0)
+    got = o.l2p_batch(P, centres, pts, Ms[:, : size(P)], nthreads=2)
+    for c in range(count):
+        for j in range(npts):
+            if not np.array_equal(got[c, j], o.l2p(P, centres[c], Ms[c, : size(P)], pts[c, j])):
+                worst = max(worst, 1.0)
+    return worst, 0.0
+
+
 PINS = [
     pin_regular_closed_form,
     pin_singular_closed_form,
@@ -524,4 +589,5 @@ PINS = [
     pin_eval_m_far_field,
     pin_l2p_gradient_finite_difference,
     pin_l2p_vs_direct_field,
+    pin_batch_entry_points,
 ]

@@ -40,6 +40,11 @@ MUTANTS = [
     ("l2p_dz_index", "get_r(R, n - 1, m, &cr, &ci);", "get_r(R, n - 1, m + 1, &cr, &ci);", None),
     ("l2p_dx_neighbour", "get_r(R, n - 1, m + 1, &br, &bi);", "get_r(R, n - 1, m, &br, &bi);", None),
     ("l2l_first_term_dropped", "for (int n = k; n < p_in; ++n) {", "for (int n = k + 1; n < p_in; ++n) {", None),
+    ("batch_op_codes_swapped", "if (op == 0)\n            or_m2m", "if (op == 2)\n            or_m2m", None),
+    ("batch_input_stride_from_ld_out", "const real *src = in + i * ld_in;", "const real *src = in + i * ld_out;",
+     None),
+    ("p2m_batch_point_stride", "or_p2m(P, centres + 3 * c, npts, pts + 3 * npts * c,",
+     "or_p2m(P, centres + 3 * c, npts, pts + npts * c,", None),
 ]
 
 
