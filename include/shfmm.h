@@ -403,9 +403,9 @@ void sh_fmm_destroy(sh_fmm *fmm);
 /* One evaluation on device pointers, stream-ordered: pts (N x 3, leaf by leaf), charges q
  * (N), out (N x 4) receives {u, du/dx, du/dy, du/dz} at every particle (the field is minus
  * the gradient).  N = 8^levels * npts.  By default the evaluation is captured once per
- * (pts, q, out) into a HIP graph (the near field on a branch of its own, the M2L of each
- * level on its own branch) and replayed; flags = SH_FMM_NO_GRAPH launches every kernel on
- * hip_stream instead.  Errors: SH_EINVAL (null pointer, unknown flags), SH_EDEVICE. */
+ * (pts, q, out) into a HIP graph (the near field on a branch of its own; the far field,
+ * P2M to L2P, on the caller's stream) and replayed; flags = SH_FMM_NO_GRAPH launches every
+ * kernel on hip_stream instead.  Errors: SH_EINVAL (null pointer, unknown flags), SH_EDEVICE. */
 #define SH_FMM_NO_GRAPH 1u
 sh_status sh_fmm_evaluate(sh_fmm *fmm, const double *pts, const double *q, double *out,
                           unsigned flags, void *hip_stream);

@@ -396,17 +396,23 @@ hipError_t capture(sh_fmm *f, const double *pts, const double *q, double *out)
         f->exec = nullptr;
     }
     if (!f->cap) {
-        if ((e = hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking)) != hipSuccess) return e;
-        {
-            hipStream_t st;
-            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
-            f->side.push_back(st);
+        // created into locals and kept only when all of them exist, so a failed creation
+        // leaves the handle as it was and the next evaluation tries again
+        hipStream_t cap = nullptr, side = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            if (side) (void)hipStreamDestroy(side);
+            if (cap) (void)hipStreamDestroy(cap);
+            return e;
         }
-        for (int i = 0; i < 2; ++i) {
-            hipEvent_t ev;
-            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
-            f->ev.push_back(ev);
-        }
+        f->side.assign(1, side);
+        f->ev.assign(ev, ev + 2);
+        f->cap = cap;
     }
     if ((e = hipStreamBeginCapture(f->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
     const hipError_t le = enqueue(f, pts, q, out, f->cap, true);
