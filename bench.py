@@ -200,23 +200,15 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     return res
 
 
-def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, staging=10 << 20):
-    """The serving workload: a Poisson stream (mean `rate` jobs/s, for `seconds`) of jobs of
-    10^3..10^5 translations (log-uniform), one order P in {4, 8, 16, 24, 30} and one dtype
-    (FP32 or FP64) per job, on resident trees (one per order and dtype, n_slots multipoles and
-    locals each).  Operations M2M / M2L / L2L with probabilities 0.2 / 0.6 / 0.2; M2M and L2L
-    read the first half of a pool and write the second.  The staging budget (admission by
-    footprint, 80 B per translation) holds one of the largest jobs (8 MB), so admission defers
-    jobs under bursts.  Latency: submission to completion."""
-    from paper_2202_02847_amd import workloads as wl
+SERVE_ORDERS = [4, 8, 16, 24, 30]
 
-    orders = [4, 8, 16, 24, 30]
-    dts = [sh.SH_F64, sh.SH_F32]
-    pool = sum(2 * n_slots * P * (P + 1) * (8 if dt == sh.SH_F64 else 4) for P in orders for dt in dts)
-    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=staging, streams=4, max_batch_jobs=64)
+
+def _serving_trees(sh, srv, n_slots):
+    """One resident tree per (order, dtype) of the serving workload, pools filled with a tiled
+    random block (the values do not change the work)."""
     trees = {}
-    for P in orders:
-        for dt in dts:
+    for P in SERVE_ORDERS:
+        for dt in (sh.SH_F64, sh.SH_F32):
             t = srv.tree_create(dt, P, n_slots, P, n_slots)
             npdt = np.float64 if dt == sh.SH_F64 else np.float32
             block = np.random.default_rng(P).normal(size=(1024, P * (P + 1))).astype(npdt) * 1e-2
@@ -224,37 +216,31 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
                 for first in range(0, n_slots, 1024):
                     srv.tree_write(t, pool_id, first, block[: min(1024, n_slots - first)])
             trees[(P, dt)] = t
-    rng = wl.rng_for(5, 0)
-    ops = ["m2m", "m2l", "l2l"]
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5)))
-    arrivals = arrivals[arrivals < seconds]
-    ids = []
-    log(f"[bench] serving {len(arrivals)} jobs over {seconds:.0f} s")
-    t0 = time.perf_counter()
-    for k, a in enumerate(arrivals):
-        if k and k % 2000 == 0:
-            log(f"[bench] serving: {k} jobs submitted")
-        P = orders[rng.integers(len(orders))]
-        dt = dts[rng.integers(2)]
-        op = ops[rng.choice(3, p=[0.2, 0.6, 0.2])]
-        count = int(10 ** rng.uniform(3, 5))
-        r = wl.random_shifts(rng, count, 2.0, 6.0)
-        if op == "m2l":
-            src = rng.integers(0, n_slots, count)
-            dst = (rng.integers(n_slots) + np.arange(count)) % n_slots
-        else:
-            half = n_slots // 2
-            src = rng.integers(0, half, count)
-            dst = half + (rng.integers(half) + np.arange(count)) % half
-        delay = t0 + a - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        ids.append(srv.submit(trees[(P, dt)], op, r, src, dst))
-    srv.drain()
-    for i in ids:
-        srv.wait(i)
-    st = srv.stats()
-    srv.close()
+    return trees
+
+
+def _serving_job(sh, rng, n_slots):
+    """One job of the serving workload: order, dtype, operation, shifts, source and destination
+    slots.  M2L reads random multipole slots and writes a run of distinct local slots; M2M and
+    L2L read the first half of a pool and write the second."""
+    from paper_2202_02847_amd import workloads as wl
+
+    P = SERVE_ORDERS[rng.integers(len(SERVE_ORDERS))]
+    dt = (sh.SH_F64, sh.SH_F32)[rng.integers(2)]
+    op = ("m2m", "m2l", "l2l")[rng.choice(3, p=[0.2, 0.6, 0.2])]
+    count = int(10 ** rng.uniform(3, 5))
+    r = wl.random_shifts(rng, count, 2.0, 6.0)
+    if op == "m2l":
+        src = rng.integers(0, n_slots, count)
+        dst = (rng.integers(n_slots) + np.arange(count)) % n_slots
+    else:
+        half = n_slots // 2
+        src = rng.integers(0, half, count)
+        dst = half + (rng.integers(half) + np.arange(count)) % half
+    return P, dt, op, r, src, dst
+
+
+def _serving_stats(st, rate, staging):
     return {"jobs": st["jobs_done"], "failed": st["jobs_failed"], "offered_jobs_per_s": rate,
             "duration_s": round(st["elapsed_s"], 3),
             "translations_per_s": st["translations_done"] / max(st["elapsed_s"], 1e-9),
@@ -263,6 +249,91 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
             "batches": st["batches"], "queue_peak": st["queue_peak"], "jobs_deferred": st["jobs_deferred"],
             "staging_budget_mb": round(staging / 2 ** 20, 1),
             "staging_peak_mb": round(st["staging_peak_bytes"] / 2 ** 20, 1)}
+
+
+def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, staging=10 << 20,
+                sat_jobs=600):
+    """The serving workload: a Poisson stream (mean `rate` jobs/s, for `seconds`) of jobs of
+    10^3..10^5 translations (log-uniform), one order P in {4, 8, 16, 24, 30} and one dtype
+    (FP32 or FP64) per job, on resident trees (one per order and dtype, n_slots multipoles and
+    locals each).  Operations M2M / M2L / L2L with probabilities 0.2 / 0.6 / 0.2.  The staging
+    budget (admission by footprint, 80 B per translation) holds one of the largest jobs (8 MB),
+    so admission defers jobs under bursts.  Latency: submission to completion.
+
+    Then a saturation leg: `sat_jobs` jobs of the same distribution queued at once (closed
+    loop), through a new server with a staging budget 8x larger, against the same job stream
+    issued as plain calls: one indexed batched call per job on one stream, its shift and slot
+    arrays copied from pinned host memory before each call."""
+    pool = sum(2 * n_slots * P * (P + 1) * (8 if dt == sh.SH_F64 else 4) for P in SERVE_ORDERS
+               for dt in (sh.SH_F64, sh.SH_F32))
+    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=staging, streams=4, max_batch_jobs=64)
+    trees = _serving_trees(sh, srv, n_slots)
+    from paper_2202_02847_amd import workloads as wl
+
+    rng = wl.rng_for(5, 0)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5)))
+    arrivals = arrivals[arrivals < seconds]
+    ids = []
+    log(f"[bench] serving {len(arrivals)} jobs over {seconds:.0f} s")
+    t0 = time.perf_counter()
+    for k, a in enumerate(arrivals):
+        if k and k % 2000 == 0:
+            log(f"[bench] serving: {k} jobs submitted")
+        P, dt, op, r, src, dst = _serving_job(sh, rng, n_slots)
+        delay = t0 + a - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(trees[(P, dt)], op, r, src, dst))
+    srv.drain()
+    for i in ids:
+        srv.wait(i)
+    res = _serving_stats(srv.stats(), rate, staging)
+    srv.close()
+
+    # ---- saturation: every job queued at once, served vs plain calls ----
+    log(f"[bench] serving saturation: {sat_jobs} jobs")
+    rng = wl.rng_for(5, 1)
+    jobs = [_serving_job(sh, rng, n_slots) for _ in range(sat_jobs)]
+    sat_staging = 8 * staging
+    srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=sat_staging, streams=4, max_batch_jobs=64)
+    trees = _serving_trees(sh, srv, n_slots)
+    ids = [srv.submit(trees[(P, dt)], op, r, src, dst) for P, dt, op, r, src, dst in jobs]
+    srv.drain()
+    for i in ids:
+        srv.wait(i)
+    sat = _serving_stats(srv.stats(), None, sat_staging)
+    srv.close()
+    torch.cuda.empty_cache()
+    # the plain path: resident pools as torch tensors, one indexed call per job on one stream
+    pools = {}
+    for P in SERVE_ORDERS:
+        for dt in (sh.SH_F64, sh.SH_F32):
+            tdt = torch.float64 if dt == sh.SH_F64 else torch.float32
+            pools[(P, dt)] = [torch.full((n_slots, P * (P + 1)), 1e-2, dtype=tdt, device=dev) for _ in range(2)]
+    staged = []
+    for P, dt, op, r, src, dst in jobs:
+        npdt = np.float64 if dt == sh.SH_F64 else np.float32
+        staged.append((P, dt, op, len(src), torch.from_numpy(r.astype(npdt)).pin_memory(),
+                       torch.from_numpy(src.astype(np.int64)).pin_memory(),
+                       torch.from_numpy(dst.astype(np.int64)).pin_memory()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for P, dt, op, count, r, src, dst in staged:
+        d_r, d_s, d_d = (x.to(dev, non_blocking=True) for x in (r, src, dst))
+        Mp, Lp = pools[(P, dt)]
+        S = P * (P + 1)
+        inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
+        sh.sh_translate_indexed(ctx, op, dt, P, P, count, d_r, d_s, inp, S, d_d, out, S)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ntr = sum(len(j[4]) for j in jobs)
+    sat["plain_translations_per_s"] = ntr / t_plain
+    sat["plain_s"] = round(t_plain, 4)
+    sat["served_over_plain"] = round(sat["translations_per_s"] / sat["plain_translations_per_s"], 3)
+    res["saturation"] = sat
+    del pools, staged
+    torch.cuda.empty_cache()
+    return res
 
 
 def l2p_flops_per_target(P):

@@ -251,11 +251,15 @@ void sh_shared_destroy(sh_shared *shared);
  *   M2L: tree M pool slot src[i] -> L pool slot dst[i]  (orders p_m -> p_l);
  *   M2M: M pool -> M pool;  L2L: L pool -> L pool;
  * with shift r[3i..3i+2] (host arrays, copied at submission).  Destinations are unique within
- * a job, and for M2M / L2L no destination is also a source.  Jobs are admitted by footprint
- * (80 bytes of staging per translation plus 2 KiB) while the staging arena has room and
- * their tree has no job in flight; every admissible job joins the next batch, which runs as
- * one mixed work list per (dtype, accumulate) group on the least loaded stream, so batches
- * overlap on the device.  A translation's result does not depend on the batch it ran in.
+ * a job, and for M2M / L2L no destination is also a source.  Jobs are admitted in submission
+ * order with backfill, by footprint (80 bytes of staging per translation plus 2 KiB: the
+ * device memory a job holds while in flight; the pools are reserved at tree creation), while
+ * the staging arena has room and nothing in flight on their tree conflicts: overwriting M2L
+ * jobs (no SH_ACCUMULATE) share a tree while their destination slots are disjoint, M2M, L2L
+ * and accumulating jobs run alone on their tree, and a job passed over holds back every later
+ * job of its tree.  Every admissible job joins the next batch, which runs as one mixed work
+ * list per (dtype, accumulate) group on the least loaded stream, so batches overlap on the
+ * device.  A translation's result does not depend on the batch it ran in.
  * Thread safety: every call may come from any host thread. */
 typedef struct sh_server sh_server;
 
@@ -415,8 +419,9 @@ sh_status sh_fmm_evaluate(sh_fmm *fmm, const double *pts, const double *q, doubl
  * tree with uniformly distributed particles and charges of both signs.  The rule comes from
  * this driver's measured error against direct summation: below 0.15 * 0.444^P at order P on
  * every level, and no lower when a single level's order is raised, so every level takes the
- * smallest P meeting tol (capped at SH_MAX_ORDER).  Host only.  Errors: SH_EINVAL (NULL
- * orders, tol outside (0, 1), levels outside [2, SH_FMM_MAX_LEVELS]). */
+ * smallest P meeting tol.  It is applied only within its measured range: trees of 2 to 4
+ * levels and orders up to 18 (tol >= 6.6e-8).  Host only.  Errors: SH_EINVAL (NULL orders,
+ * tol outside (0, 1), levels outside [2, 4]), SH_EORDER (tol needs an order above 18). */
 sh_status sh_fmm_orders_for_tolerance(double tol, int levels, int *orders);
 
 /* counts[0..4] = M2M, M2L and L2L translations per evaluation, translation calls, leaves. */

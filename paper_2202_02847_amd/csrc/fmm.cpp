@@ -455,14 +455,18 @@ sh_status sh_fmm_evaluate(sh_fmm *f, const double *pts, const double *q, double 
 // trees, 3 levels, 8-24 uniform particles per leaf, charges uniform in [-1, 1], four seeds):
 // every measurement lies below kErrC * kErrRho^P (P = 4..14).  Lowering one level's order
 // raises the error to that order's level and raising one level alone does not lower it, so
-// every level takes the same order.
+// every level takes the same order.  The rule is used only where it was measured, with a
+// margin: orders up to kRuleMaxOrder and trees of 2 to kRuleMaxLevels levels (the tests check
+// it on 2-, 3- and 4-level trees); targets below kErrC * kErrRho^kRuleMaxOrder (6.6e-8, far
+// above the FP64 rounding of the potential, about 1e-15) are refused.
 constexpr double kErrC = 0.15, kErrRho = 0.444;
+constexpr int kRuleMaxOrder = 18, kRuleMaxLevels = 4;
 
 sh_status sh_fmm_orders_for_tolerance(double tol, int levels, int *orders)
 {
-    if (!orders || !(tol > 0.0) || !(tol < 1.0) || levels < 2 || levels > SH_FMM_MAX_LEVELS) return SH_EINVAL;
-    int P = (int)std::ceil(std::log(tol / kErrC) / std::log(kErrRho) - 1e-9);
-    P = std::max(1, std::min(P, SH_MAX_ORDER));
+    if (!orders || !(tol > 0.0) || !(tol < 1.0) || levels < 2 || levels > kRuleMaxLevels) return SH_EINVAL;
+    const int P = std::max(1, (int)std::ceil(std::log(tol / kErrC) / std::log(kErrRho) - 1e-9));
+    if (P > kRuleMaxOrder) return SH_EORDER;
     for (int l = 2; l <= levels; ++l) orders[l - 2] = P;
     return SH_OK;
 }

@@ -5,7 +5,11 @@
 // * Admission by HBM footprint.  A job's footprint is the device staging its work records
 //   take while it is in flight (an upper bound of 80 bytes per translation plus 2 KiB);
 //   jobs are admitted, first come first served with backfill, while the staging arena has
-//   room and their tree has no job in flight.
+//   room and nothing in flight on their tree conflicts with them: M2L jobs that overwrite
+//   (no SH_ACCUMULATE) only read the multipole pool, so several of them run together on one
+//   tree while their destination slots are disjoint; M2M, L2L and accumulating jobs run alone
+//   on their tree.  A job passed over keeps every later job of its tree waiting, so jobs that
+//   touch the same slots complete in submission order.
 // * Continuous batching.  The scheduler thread fuses every admissible job into one batch:
 //   one mixed work list per (dtype, accumulate) group, binned and launched like a plan, on
 //   the least loaded of a few streams, so batches overlap on the device and jobs arriving
@@ -97,9 +101,15 @@ struct Tree {
     int64_t n_m = 0, n_l = 0;
     int64_t off_m = 0, off_l = 0;  // byte offsets in the pool arena
     int64_t bytes_m = 0, bytes_l = 0;
-    bool busy = false;             // a job on this tree is in flight
+    int running = 0;               // jobs of this tree reserved for a batch or in flight
+    bool exclusive = false;        // one of them needs the tree alone
+    std::vector<unsigned char> claim;  // local slots written by running shared M2L jobs
     int pending = 0;               // jobs queued or in flight
 };
+
+// An overwriting M2L reads only multipoles and writes only its destination locals, so jobs of
+// this kind share a tree while their destinations are disjoint.
+bool shares_tree(int op, unsigned flags) { return op == SH_M2L && !(flags & SH_ACCUMULATE); }
 
 struct Job {
     int32_t tree = 0, op = 0;
@@ -194,6 +204,19 @@ void job_items(const Tree &t, const Job &j, std::vector<ListItem> &out)
     }
 }
 
+// Reserves (on) or releases (off) a job's claim on its tree: the running count, the tree
+// alone for a job that does not share it, the destination slots for one that does.  Called
+// with the server lock held.
+void reserve_job(Tree &t, const Job &j, bool on)
+{
+    t.running += on ? 1 : -1;
+    if (shares_tree(j.op, j.flags)) {
+        for (int64_t d : j.dst) t.claim[(size_t)d] = on ? 1 : 0;
+    } else {
+        t.exclusive = on;
+    }
+}
+
 // Builds and launches one batch (called by the scheduler without the lock; the batch's jobs
 // and trees are reserved, so nothing it reads changes meanwhile).
 hipError_t launch_batch(sh_server *S, Batch &b)
@@ -272,31 +295,45 @@ void scheduler_main(sh_server *S)
         if (stream >= 0 && !S->queue.empty()) {
             int64_t need = 0;
             std::vector<size_t> take;
-            std::vector<int32_t> claimed;
+            std::vector<int32_t> blocked;  // trees with a job passed over in this scan
             const int64_t free_total = S->stage_alloc.size - S->stage_alloc.used;
             for (size_t qi = 0; qi < S->queue.size() && (int)take.size() < S->cfg.max_batch_jobs; ++qi) {
-                const Job &j = *S->jobs.at(S->queue[qi]);
+                Job &j = *S->jobs.at(S->queue[qi]);
                 Tree &t = S->trees.at(j.tree);
-                if (t.busy || std::find(claimed.begin(), claimed.end(), j.tree) != claimed.end()) continue;
-                if (need + j.footprint > free_total) {
-                    Job &jm = *S->jobs.at(S->queue[qi]);
-                    if (!jm.deferred) {
-                        jm.deferred = true;
+                if (std::find(blocked.begin(), blocked.end(), j.tree) != blocked.end()) continue;
+                const bool shared = shares_tree(j.op, j.flags);
+                bool fits = shared ? !t.exclusive : t.running == 0;
+                if (fits && shared) {
+                    if (t.claim.size() != (size_t)t.n_l) t.claim.assign((size_t)t.n_l, 0);
+                    for (int64_t d : j.dst)
+                        if (t.claim[(size_t)d]) {
+                            fits = false;
+                            break;
+                        }
+                }
+                if (fits && need + j.footprint > free_total) {
+                    fits = false;
+                    if (!j.deferred) {
+                        j.deferred = true;
                         ++S->jobs_deferred;
                     }
+                }
+                if (!fits) {
+                    blocked.push_back(j.tree);
                     continue;
                 }
+                reserve_job(t, j, true);
                 need += j.footprint;
                 take.push_back(qi);
-                claimed.push_back(j.tree);
             }
             if (!take.empty()) {
                 int64_t off = S->stage_alloc.alloc(need);
-                while (off < 0 && take.size() > 1) {  // fragmentation: shrink the batch
-                    need -= S->jobs.at(S->queue[take.back()])->footprint;
+                while (off < 0 && !take.empty()) {  // fragmentation: shrink the batch
+                    Job &j = *S->jobs.at(S->queue[take.back()]);
+                    reserve_job(S->trees.at(j.tree), j, false);
+                    need -= j.footprint;
                     take.pop_back();
-                    claimed.pop_back();
-                    off = S->stage_alloc.alloc(need);
+                    off = take.empty() ? -1 : S->stage_alloc.alloc(need);
                 }
                 if (off >= 0) {
                     b.stream = stream;
@@ -311,7 +348,6 @@ void scheduler_main(sh_server *S)
                     for (int64_t id : b.jobs) {
                         Job *j = S->jobs.at(id).get();
                         Tree &t = S->trees.at(j->tree);
-                        t.busy = true;
                         b.jp.push_back(j);
                         b.tp.push_back(&t);
                         b.translations += (int64_t)j->src.size();
@@ -366,7 +402,7 @@ void completer_main(sh_server *S, int stream)
             j.t_done = t;
             if (e != hipSuccess) j.status = SH_EDEVICE;
             Tree &tr = S->trees.at(j.tree);
-            tr.busy = false;
+            reserve_job(tr, j, false);
             --tr.pending;
             if (j.status == SH_OK) {
                 S->latencies.push_back(t - j.t_submit);

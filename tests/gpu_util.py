@@ -97,67 +97,110 @@ def dense_operator(orc, op, p_in, p_out, r):
     return T * s_out[:, None] / s_in[None, :]
 
 
-def degree_kappa(orc, op, p_in, p_out, r, C):
-    """Cancellation factor per output degree n of one translation: max_m sum_k |T_hat||a_hat| over
-    max_m |L_hat_ref| in the normalised basis.  An FP32 evaluation errs by a few rounding units
-    of the terms it sums, so its relative error in a degree grows by this factor."""
-    T = dense_operator(orc, op, p_in, p_out, r)
-    w_in, w_out = weights_flat(p_in), weights_flat(p_out)
-    a = np.abs(C * (w_in if IN_KIND[op] == "M" else 1.0 / w_in))
-    for nn in range(p_in):
-        a[nn * (nn + 1) + 1] = 0.0
-    s_out = w_out if OUT_KIND[op] == "M" else 1.0 / w_out
-    ref = orc.translate_batch(op, p_in, p_out, np.reshape(r, (1, 3)), C[None, :])[0] * s_out
-    mag = np.abs(T) @ a
-    kap = np.zeros(p_out)
-    for nn in range(p_out):
-        sl = slice(nn * (nn + 1), (nn + 1) * (nn + 2))
-        kap[nn] = mag[sl].max() / max(np.abs(ref[sl]).max(), 1e-300)
-    return kap
+class Plain32:
+    """A plain FP32 evaluation of the same translations, as the reference for FP32 bounds.
+
+    Each output of a translation is a dot product sum_k T_hat[i, k] a_k of the translation's
+    dense operator (normalised basis) with its input.  Here the operator is built exactly
+    (the FP64 oracle applied to unit solids, for the shift rounded to FP32, as the FP32 entry
+    points receive it) and rounded once to FP32, the input is the FP32 normalised solid the GPU
+    receives, and the products and sums are formed one by one in FP32 (each rounded, no
+    fused multiply-add), starting from the FP32 initial output for an accumulating call.  Its
+    per-degree error against the exact result measures what FP32 arithmetic costs on that
+    input: where a degree's coefficients cancel, every FP32 evaluation errs by a few rounding
+    units of sum_k |T_hat| |a_k| rather than of the result.
+
+    apply(r_rows, C_rows) -> output rows is the oracle's operation (paper basis)."""
+
+    def __init__(self, apply, p_in, p_out, in_kind, out_kind, r, C, base=None):
+        self.apply, self.p_in, self.p_out = apply, p_in, p_out
+        self.in_kind, self.out_kind = in_kind, out_kind
+        self.r = np.asarray(r, np.float32).astype(np.float64).reshape(-1, 3)
+        self.C = np.asarray(C, np.float64).reshape(self.r.shape[0], -1)
+        self.base = None if base is None else np.asarray(base, np.float64)
+        self._ops = {}
+
+    def operator(self, r):
+        key = tuple(r)
+        if key not in self._ops:
+            K = self.p_in * (self.p_in + 1)
+            T = self.apply(np.repeat(np.reshape(r, (1, 3)), K, axis=0), np.eye(K)).T
+            w_in, w_out = weights_flat(self.p_in), weights_flat(self.p_out)
+            s_in = w_in if self.in_kind == "M" else 1.0 / w_in
+            s_out = w_out if self.out_kind == "M" else 1.0 / w_out
+            self._ops[key] = (T * s_out[:, None] / s_in[None, :]).astype(np.float32)
+        return self._ops[key]
+
+    def result(self, i):
+        """The plain FP32 evaluation of translation i (paper basis, FP64 array)."""
+        T = self.operator(self.r[i])
+        a = to_basis(self.C[i, : self.p_in * (self.p_in + 1)], self.p_in, self.in_kind, sh.SH_F32)
+        if self.base is None:
+            y = np.zeros(T.shape[0], np.float32)
+        else:
+            y = to_basis(self.base[i], self.p_out, self.out_kind, sh.SH_F32)
+        for k in range(T.shape[1]):
+            y = y + T[:, k] * a[k]
+        return from_basis(y, self.p_out, self.out_kind, sh.SH_F32)
+
+    def error(self, i, ref_i):
+        return max_degree_error(self.result(i), ref_i, self.p_out, self.out_kind)
 
 
-def check(got, ref, p_out, kind, tol, what, ref_ld=None, ref_in32=None, cond=None):
-    """ref_ld: long-double reference (FP64 path).  ref_in32: the FP64 oracle applied to the
-    input rounded through the FP32 normalised basis -- its distance from ref is the error
-    any FP32-input computation inherits; the FP32 bound is max(tol, COND_FACTOR x that).
-    cond = (orc, op, p_in, r, C): for a translation above that bound, the per-degree FP32
-    bound becomes max(bound, 4 u kappa_n) with u = 2^-24 and kappa_n from degree_kappa."""
+def plain32_for(orc, op, p_in, p_out, r, C, base=None):
+    """Plain32 for a batched M2M / M2L / L2L."""
+    return Plain32(lambda rr, CC: orc.translate_batch(op, p_in, p_out, rr, CC, nthreads=8), p_in, p_out,
+                   IN_KIND[op], OUT_KIND[op], r, C, base)
+
+
+# FP32 bound per translation: max(tol, PLAIN32_FACTOR x the error of the plain FP32 evaluation
+# of the same translation, Plain32).  FP32 results of the rotation path, of the FP64-arithmetic
+# path at high orders and of the matrix-core forms all round at different places than the plain
+# dot products; a factor 2 allows for that and nothing more.
+PLAIN32_FACTOR = 2.0
+
+
+class BoundStats:
+    """Per check: how many translations needed more than the flat tolerance, and the worst."""
+
+    def __init__(self):
+        self.over = 0
+        self.worst_over = 0.0
+
+    def note(self, e, tol):
+        if e > tol:
+            self.over += 1
+            self.worst_over = max(self.worst_over, e)
+
+
+def check(got, ref, p_out, kind, tol, what, ref_ld=None, plain32=None, factor32=PLAIN32_FACTOR):
+    """Per-translation C15 error of got against the oracle.
+
+    FP64 (ref_ld = long-double oracle): error against ref_ld, bound max(tol, COND_FACTOR x the
+    FP64 oracle's own error against ref_ld).  FP32 (plain32 = Plain32 of the same inputs): error
+    against ref, bound max(tol, factor32 x the plain FP32 evaluation's error), computed only for
+    translations above tol.  Otherwise: error against ref, bound tol.  Prints how many
+    translations needed more than tol and the worst of them.  Returns the worst error."""
     worst = 0.0
+    st = BoundStats()
     for i in range(ref.shape[0]):
-        if ref_in32 is not None:
-            floor = max_degree_error(ref_in32[i], ref[i], p_out, kind)
-            bound = max(tol, COND_FACTOR * floor)
-            e = max_degree_error(got[i], ref[i], p_out, kind)
-        elif ref_ld is not None:
+        if ref_ld is not None:
             own = max_degree_error(ref[i], ref_ld[i], p_out, kind)
             bound = max(tol, COND_FACTOR * own)
             e = max_degree_error(got[i], ref_ld[i], p_out, kind)
         else:
-            bound = tol
             e = max_degree_error(got[i], ref[i], p_out, kind)
-        if e > bound and cond is not None:
-            orc, op, p_in, r, C = cond
-            kap = degree_kappa(orc, op, p_in, p_out, r[i], C[i])
-            base = ref_ld[i] if ref_ld is not None else ref[i]
-            for nn in range(p_out):
-                sl = slice(nn * (nn + 1), (nn + 1) * (nn + 2))
-                w = weights_flat(p_out)[sl]
-                s = w if kind == "M" else 1.0 / w
-                den = max(np.abs(base[sl] * s).max(), 1e-300)
-                en = np.abs((got[i][sl] - base[sl]) * s).max() / den
-                bn = max(bound, 4.0 * 2.0 ** -24 * kap[nn])
-                assert en <= bn, f"{what} translation {i} degree {nn}: {en:.3e} > {bn:.1e} (kappa {kap[nn]:.1e})"
-            worst = max(worst, e)
-            continue
+            bound = tol
+            if e > tol and plain32 is not None:
+                pe = plain32.error(i, ref[i])
+                bound = max(tol, factor32 * pe)
+                assert e <= bound, f"{what} translation {i}: {e:.3e} > {bound:.2e} (plain FP32 {pe:.2e})"
+        st.note(e, tol)
         worst = max(worst, e)
         assert e <= bound, f"{what} translation {i}: {e:.3e} > {bound:.1e}"
+    if st.over:
+        print(f"[bound] {what}: {st.over} of {ref.shape[0]} above {tol:.0e}, worst {st.worst_over:.2e}", flush=True)
     return worst
-
-
-def in32_ref(orc, op, p_in, p_out, r, C):
-    C32 = from_basis(to_basis(C, p_in, IN_KIND[op], sh.SH_F32), p_in, IN_KIND[op], sh.SH_F32)
-    r32 = np.asarray(r, np.float32).astype(np.float64)
-    return orc.translate_batch(op, p_in, p_out, r32, C32)
 
 
 def ld_ref(op, p_in, p_out, r, C):

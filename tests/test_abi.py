@@ -89,16 +89,20 @@ def test_normalise_roundtrip():
 
 def test_fmm_orders_for_tolerance():
     """Host-only order selection: one order for every level, growing as the target shrinks,
-    the smallest P with 0.15 * 0.444^P <= tol; bad arguments rejected."""
+    the smallest P with 0.15 * 0.444^P <= tol; targets needing an order above the rule's
+    measured range (18) and trees outside 2..4 levels refused."""
     prev = 0
-    for tol in (0.5, 1e-2, 1e-3, 1e-5, 1e-8, 1e-12):
-        orders = sh.sh_fmm_orders_for_tolerance(tol, 4)
-        assert len(orders) == 3 and len(set(orders)) == 1
+    for tol in (0.5, 1e-2, 1e-3, 1e-5, 1e-7):
+        for levels in (2, 3, 4):
+            orders = sh.sh_fmm_orders_for_tolerance(tol, levels)
+            assert len(orders) == levels - 1 and len(set(orders)) == 1
         P = orders[0]
         assert P >= prev
         prev = P
         assert P == 1 or 0.15 * 0.444 ** P <= tol * (1 + 1e-12)
         assert P == 1 or 0.15 * 0.444 ** (P - 1) > tol
-    for tol, levels in ((0.0, 3), (1.0, 3), (1e-3, 1), (1e-3, 7)):
-        with pytest.raises(sh.ShError):
+    for tol, levels, status in ((0.0, 3, sh.SH_EINVAL), (1.0, 3, sh.SH_EINVAL), (1e-3, 1, sh.SH_EINVAL),
+                                (1e-3, 5, sh.SH_EINVAL), (1e-8, 3, sh.SH_EORDER), (1e-15, 3, sh.SH_EORDER)):
+        with pytest.raises(sh.ShError) as e:
             sh.sh_fmm_orders_for_tolerance(tol, levels)
+        assert e.value.status == status

@@ -59,14 +59,15 @@ def _direct(pts, q, targets=None):
     qq = q.reshape(-1)
     idx = np.arange(len(x)) if targets is None else targets
     out = np.zeros((len(idx), 4))
-    for a in range(0, len(idx), 256):
-        ii = idx[a: a + 256]
+    step = max(1, min(256, (1 << 23) // len(x)))  # targets per pass: about 200 MB of differences
+    for a in range(0, len(idx), step):
+        ii = idx[a: a + step]
         d = x[ii][:, None, :] - x[None, :, :]
         r = np.sqrt(np.sum(d * d, axis=2))
         r[np.arange(len(ii)), ii] = np.inf
         inv = 1.0 / r
-        out[a: a + 256, 0] = inv @ qq
-        out[a: a + 256, 1:] = -np.einsum("ij,ijk->ik", (inv ** 3) * qq[None, :], d)
+        out[a: a + step, 0] = inv @ qq
+        out[a: a + step, 1:] = -np.einsum("ij,ijk->ik", (inv ** 3) * qq[None, :], d)
     return out
 
 
@@ -139,8 +140,10 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+# Leaves of at most 32 particles share a wavefront in L2P and the near field; larger leaves
+# take one wavefront per 64 targets (40: one partial chunk, 70 and 130: several chunks).
 @pytest.mark.parametrize("flags", [0, sh.SH_FMM_NO_GRAPH], ids=["graph", "eager"])
-@pytest.mark.parametrize("P,levels,npts", [(6, 2, 5), (10, 3, 9), (17, 3, 3)])
+@pytest.mark.parametrize("P,levels,npts", [(6, 2, 5), (10, 3, 9), (17, 3, 3), (8, 2, 40), (7, 2, 70), (5, 2, 130)])
 def test_fmm_matches_oracle_composition(ctx, orc, P, levels, npts, flags):
     origin, width = (-0.3, 0.1, 0.25), 2.0
     print(f"[fmm] P={P} levels={levels} npts={npts} flags={flags}", flush=True)
@@ -222,17 +225,18 @@ def test_fmm_graph_replays_match_eager(ctx):
     f.close()
 
 
+@pytest.mark.parametrize("levels,npts", [(3, 10), (2, 30), (4, 4)], ids=["3x10", "2x30", "4x4"])
 @pytest.mark.parametrize("tol", [1e-3, 1e-5])
-def test_fmm_orders_for_tolerance_meet_target(ctx, tol):
-    """Orders chosen for a target meet it against the direct sum on a tree outside the
-    measurements the rule was fitted to (10 particles per leaf, a seed not used there)."""
-    levels, npts = 3, 10
+def test_fmm_orders_for_tolerance_meet_target(ctx, tol, levels, npts):
+    """Orders chosen for a target meet it against the direct sum on trees outside the
+    measurements the rule was fitted to (3 levels with 10 particles per leaf, and the 2- and
+    4-level ends of its range, seeds not used there)."""
     origin, width = (0.0, 0.0, 0.0), 1.0
     pts, q = _particles(levels, npts, origin, width, seed=29)
     orders = sh.sh_fmm_orders_for_tolerance(tol, levels)
     got, _ = _gpu_fmm(ctx, 0, levels, origin, width, pts, q, orders=orders)
     err = _rel(got[:, 0], _direct(pts, q)[:, 0])
-    print(f"[fmm] tol={tol} orders={orders} err={err:.2e}", flush=True)
+    print(f"[fmm] levels={levels} npts={npts} tol={tol} orders={orders} err={err:.2e}", flush=True)
     assert err <= tol
 
 
@@ -249,3 +253,19 @@ def test_fmm_rejects_bad_arguments(ctx):
         sh.Fmm(ctx, 0, 3, (0, 0, 0), 1.0, 8, orders=[10, 0])  # an order below 1
     with pytest.raises(sh.ShError):
         sh.Fmm(ctx, 10, 3, (0, 0, 0), 1.0, 1 << 62)  # more than 2^31 particles (no overflow)
+
+
+def test_fmm_bench_size_sampled_vs_direct(ctx):
+    """The benchmark's FMM (4 levels x 64 uniform particles = 262,144, P = 10): 512 sampled
+    particles against the direct sum.  The error is the method's truncation error at P = 10
+    (about 2e-5 in the potential for these trees; 1e-4 is the bound)."""
+    levels, npts, P = 4, 64, 10
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=11)
+    got, desc = _gpu_fmm(ctx, P, levels, origin, width, pts, q)
+    assert desc["leaves"] == 4096 and np.isfinite(got).all()
+    pick = np.sort(np.random.default_rng(1).choice(q.size, 512, replace=False))
+    exact = _direct(pts, q, pick)
+    e_u, e_g = _rel(got[pick, 0], exact[:, 0]), _rel(got[pick, 1:], exact[:, 1:])
+    print(f"[fmm] 262144 particles P=10: sampled error potential {e_u:.2e} gradient {e_g:.2e}", flush=True)
+    assert e_u <= 1e-4 and e_g <= 1e-3

@@ -11,7 +11,7 @@ import oracle
 import paper_2202_02847_amd as sh
 from paper_2202_02847_amd import arena
 from paper_2202_02847_amd import workloads as wl
-from gpu_util import TOL, IN_KIND, OUT_KIND, check, from_basis, in32_ref, ld_ref, to_basis, torch_dev
+from gpu_util import TOL, IN_KIND, OUT_KIND, check, from_basis, ld_ref, plain32_for, to_basis, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -106,15 +106,12 @@ def check_items(orc, dtype, op, p_in, p_out, r, C, got, what, base=None):
         ref = orc.translate_batch(name, pi, po, rg, Cg)
         g = np.stack([got[i] for i in idx])
         rl = ld_ref(name, pi, po, rg, Cg) if dtype == sh.SH_F64 else None
-        r32 = in32_ref(orc, name, pi, po, rg, Cg) if dtype == sh.SH_F32 else None
-        if base is not None:
-            b = np.stack([base[i] for i in idx])
+        b = np.stack([base[i] for i in idx]) if base is not None else None
+        if b is not None:
             ref = ref + b
             rl = rl + b if rl is not None else None
-            r32 = r32 + b if r32 is not None else None
-        cond = (orc, name, pi, rg, Cg) if dtype == sh.SH_F32 else None
-        worst = max(worst, check(g, ref, po, OUT_KIND[name], TOL[dtype], f"{what} {name} {pi}->{po}", rl, r32,
-                                 cond))
+        p32 = plain32_for(orc, name, pi, po, rg, Cg, b) if dtype == sh.SH_F32 else None
+        worst = max(worst, check(g, ref, po, OUT_KIND[name], TOL[dtype], f"{what} {name} {pi}->{po}", rl, p32))
     return worst
 
 
@@ -227,8 +224,8 @@ def test_list_accumulate(ctx, orc, dtype):
         g = np.stack([got[i] for i in idx])
         tol = 4 * TOL[dtype]
         if dtype == sh.SH_F32:
-            r32 = in32_ref(orc, name, pi, po, r[idx], Cg) + np.stack([base[i] for i in idx])
-            check(g, ref, po, OUT_KIND[name], tol, f"acc {name}", ref_in32=r32)
+            p32 = plain32_for(orc, name, pi, po, r[idx], Cg, np.stack([base[i] for i in idx]))
+            check(g, ref, po, OUT_KIND[name], tol, f"acc {name}", plain32=p32)
         else:
             rl = ld_ref(name, pi, po, r[idx], Cg) + np.stack([base[i] for i in idx])
             check(g, ref, po, OUT_KIND[name], tol, f"acc {name}", ref_ld=rl)

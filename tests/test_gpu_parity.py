@@ -12,8 +12,8 @@ import pytest
 import oracle
 import paper_2202_02847_amd as sh
 from paper_2202_02847_amd import workloads as wl
-from gpu_util import TOL, IN_KIND, OUT_KIND, check as _check, in32_ref as _in32_ref, ld_ref as _ld_ref, \
-    run_batch, torch_dev
+from gpu_util import TOL, IN_KIND, OUT_KIND, check as _check, from_basis, ld_ref as _ld_ref, plain32_for, run_batch, \
+    to_basis, torch_dev
 from refmath import max_degree_error, size
 
 pytestmark = pytest.mark.gpu
@@ -74,8 +74,8 @@ def test_orders(ctx, orc, op, dtype, p_in, p_out):
     ref = orc.translate_batch(op, p_in, p_out, r, C)
     got, _ = run_batch(ctx, op, dtype, p_in, p_out, r, C)
     ref_ld = _ld_ref(op, p_in, p_out, r, C) if dtype == sh.SH_F64 else None
-    ref_in32 = _in32_ref(orc, op, p_in, p_out, r, C) if dtype == sh.SH_F32 else None
-    _check(got, ref, p_out, OUT_KIND[op], TOL[dtype], f"{op} {DT_ID[dtype]} {p_in}->{p_out}", ref_ld, ref_in32)
+    p32 = plain32_for(orc, op, p_in, p_out, r, C) if dtype == sh.SH_F32 else None
+    _check(got, ref, p_out, OUT_KIND[op], TOL[dtype], f"{op} {DT_ID[dtype]} {p_in}->{p_out}", ref_ld, p32)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DT_ID.get)
@@ -90,29 +90,46 @@ def test_config1_all_ops(ctx, orc, dtype):
     L2 = orc.translate_batch("l2l", P, P, c["r_l2l"], L, nthreads=8)
     for op, r, C, ref in (("m2l", c["r_m2l"], M, L), ("m2m", c["r_m2m"], M, M2), ("l2l", c["r_l2l"], L, L2)):
         got, _ = run_batch(ctx, op, dtype, P, P, r, C)
-        _check(got, ref, P, OUT_KIND[op], TOL[dtype], f"config1 {op}")
+        p32 = plain32_for(orc, op, P, P, r, C) if dtype == sh.SH_F32 else None
+        _check(got, ref, P, OUT_KIND[op], TOL[dtype], f"config1 {op}", plain32=p32)
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=DT_ID.get)
 @pytest.mark.parametrize("P", [10, 16, 30])
-def test_octree_full_size_sampled(ctx, orc, P):
+def test_octree_full_size_sampled(ctx, orc, P, dtype):
     """Octree M2L at the full batch size the benchmark times (2^20 at P=10; P=16, 30 on the
-    same generator), FP64, checked on sampled translations."""
+    same generator), checked on sampled translations: FP64 in the paper's basis, FP32 in the
+    normalised basis (2^12 samples, 2^10 at P=30)."""
     torch, dev = torch_dev()
     n = 1 << 20 if P <= 16 else 1 << 18
-    print(f"[parity] octree full-size P={P} n={n}", flush=True)
+    f32 = dtype == sh.SH_F32
+    print(f"[parity] octree full-size P={P} n={n} dtype={DT_ID[dtype]}", flush=True)
     c = wl.config2(n_m2l=n, n_child=8, P=P)
     M = orc.p2m_batch(P, np.zeros((n, 3)), c["pts"], c["q"], nthreads=16)
-    d_M = torch.from_numpy(M).to(dev)
-    d_r = torch.from_numpy(c["r_m2l"]).to(dev)
-    d_L = torch.empty((n, P * (P + 1)), dtype=torch.float64, device=dev)
-    sh.sh_m2l_batch_f64(ctx, P, P, n, d_r, d_M, P * (P + 1), d_L, P * (P + 1))
-    torch.cuda.synchronize()
+    S = P * (P + 1)
     rng = np.random.default_rng(P)
-    idx = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.integers(0, n, 250)]))
-    got = d_L[torch.from_numpy(idx).to(dev)].cpu().numpy()
-    ref = orc.translate_batch("m2l", P, P, c["r_m2l"][idx], M[idx], nthreads=8)
-    ref_ld = _ld_ref("m2l", P, P, c["r_m2l"][idx], M[idx])
-    _check(got, ref, P, "L", TOL[sh.SH_F64], f"octree P={P}", ref_ld)
+    extra = rng.choice(n, (1 << 10 if P > 16 else 1 << 12) if f32 else 250, replace=False)
+    idx = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], extra]))
+    if f32:
+        d_M = torch.from_numpy(to_basis(M, P, "M", dtype)).to(dev)
+        d_r = torch.from_numpy(c["r_m2l"].astype(np.float32)).to(dev)
+        d_L = torch.empty((n, S), dtype=torch.float32, device=dev)
+        sh.sh_m2l_batch_f32(ctx, P, P, n, d_r, d_M, S, d_L, S)
+    else:
+        d_M = torch.from_numpy(M).to(dev)
+        d_r = torch.from_numpy(c["r_m2l"]).to(dev)
+        d_L = torch.empty((n, S), dtype=torch.float64, device=dev)
+        sh.sh_m2l_batch_f64(ctx, P, P, n, d_r, d_M, S, d_L, S)
+    torch.cuda.synchronize()
+    got = from_basis(d_L[torch.from_numpy(idx).to(dev)].cpu().numpy(), P, "L", dtype)
+    ref = orc.translate_batch("m2l", P, P, c["r_m2l"][idx], M[idx], nthreads=16)
+    if f32:
+        p32 = plain32_for(orc, "m2l", P, P, c["r_m2l"][idx], M[idx])
+        worst = _check(got, ref, P, "L", TOL[dtype], f"octree P={P} f32", plain32=p32)
+    else:
+        ref_ld = _ld_ref("m2l", P, P, c["r_m2l"][idx], M[idx])
+        worst = _check(got, ref, P, "L", TOL[dtype], f"octree P={P}", ref_ld)
+    print(f"[parity] octree full-size P={P} {DT_ID[dtype]}: worst C15 error {worst:.2e} over {len(idx)}", flush=True)
     assert ctx.device_error() == 0
 
 
@@ -290,7 +307,6 @@ def test_indexed_gather_scatter(ctx, orc, dtype):
     rr = wl.random_shifts(rng, count, 2.0, 4.0)
     ref = orc.translate_batch("m2l", P, P, rr, C[src])
     npdt = np.float64 if dtype == sh.SH_F64 else np.float32
-    from gpu_util import to_basis, from_basis
     pool = torch.from_numpy(to_basis(C, P, "M", dtype).astype(npdt)).to(dev)
     outp = torch.zeros((npool, size(P)), dtype=pool.dtype, device=dev)
     d_src = torch.from_numpy(src.astype(np.int64)).to(dev)
@@ -304,6 +320,23 @@ def test_indexed_gather_scatter(ctx, orc, dtype):
     assert (got[untouched] == 0).all()
 
 
+def test_indexed_needs_both_index_arrays(ctx):
+    """The indexed kernels read both index arrays: a call with only one of them is rejected
+    with SH_EINVAL before anything is launched (a gather array with a null scatter array once
+    reached the kernel and faulted)."""
+    torch, dev = torch_dev()
+    P, count = 10, 4
+    idx = torch.zeros(count, dtype=torch.int64, device=dev)
+    pool = torch.zeros((count, size(P)), dtype=torch.float64, device=dev)
+    r = torch.full((count, 3), 2.0, dtype=torch.float64, device=dev)
+    for src, dst in ((idx, None), (None, idx)):
+        with pytest.raises(sh.ShError) as e:
+            sh.sh_translate_indexed(ctx, "m2l", sh.SH_F64, P, P, count, r, src, pool, size(P), dst, pool, size(P))
+        assert e.value.status == sh.SH_EINVAL
+    torch.cuda.synchronize()
+    assert ctx.device_error() == 0
+
+
 @pytest.mark.parametrize("op", ["m2l", "m2m", "l2l"])
 def test_single_host_calls(ctx, orc, op):
     p_in, p_out = 9, 11
@@ -313,7 +346,6 @@ def test_single_host_calls(ctx, orc, op):
         got = getattr(sh, f"sh_{op}_f64")(ctx, p_in, p_out, r[i], C[i])
         assert max_degree_error(got, ref, p_out, OUT_KIND[op]) <= TOL[sh.SH_F64]
         w_in = np.asarray(C[i], np.float64)
-        from gpu_util import to_basis, from_basis
         g32 = getattr(sh, f"sh_{op}_f32")(ctx, p_in, p_out, r[i].astype(np.float32),
                                            to_basis(w_in, p_in, IN_KIND[op], sh.SH_F32))
         assert max_degree_error(from_basis(g32, p_out, OUT_KIND[op], sh.SH_F32), ref, p_out,

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import paper_2202_02847_amd as sh
 from paper_2202_02847_amd import workloads as wl
-from gpu_util import TOL, check, from_basis, in32_ref, ld_ref, to_basis, torch_dev
+from gpu_util import TOL, check, from_basis, ld_ref, plain32_for, to_basis, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -72,9 +72,8 @@ def read_pool(srv, t, pool, P, n, dtype):
 def check_job(orc, dtype, op, P, r, C_in, got, what):
     ref = orc.translate_batch(op, P, P, r, C_in)
     rl = ld_ref(op, P, P, r, C_in) if dtype == sh.SH_F64 else None
-    r32 = in32_ref(orc, op, P, P, r, C_in) if dtype == sh.SH_F32 else None
-    cond = (orc, op, P, r, C_in) if dtype == sh.SH_F32 else None
-    return check(got, ref, P, "M" if op == "m2m" else "L", TOL[dtype], what, rl, r32, cond)
+    p32 = plain32_for(orc, op, P, P, r, C_in) if dtype == sh.SH_F32 else None
+    return check(got, ref, P, "M" if op == "m2m" else "L", TOL[dtype], what, rl, p32)
 
 
 @pytest.mark.parametrize("dtype", [sh.SH_F64, sh.SH_F32], ids=DT_ID.get)
@@ -234,3 +233,45 @@ def test_server_accumulate(ctx, orc):
     ld = ld_ref("m2l", P, P, r1, M[s1]) + ld_ref("m2l", P, P, r2, M[s2])
     check(out[d1], ref, P, "L", 4 * TOL[sh.SH_F64], "server accumulate", ld)
     srv.close()
+
+
+def test_server_shared_tree_order_and_alone_equals_mix(ctx, orc):
+    """Overwriting M2L jobs with disjoint destinations share one tree; a later M2L job that
+    overwrites some of the same slots, and an L2L job that reads what it wrote, still see the
+    submission order.  The final pools are the same (bit for bit) whether every job ran alone
+    (each waited for before the next is submitted) or all were queued at once."""
+    P, n = 8, 4000
+    rng = np.random.default_rng(404)
+    jobs = []
+    for k in range(6):  # disjoint destinations
+        dst = np.arange(500 * k, 500 * (k + 1))
+        jobs.append(("m2l", wl.random_shifts(rng, 500, 2.0, 6.0), rng.integers(0, n, 500), dst))
+    dst7 = np.concatenate([np.arange(0, 250), np.arange(3000, 3250)])  # overlaps the first job
+    jobs.append(("m2l", wl.random_shifts(rng, 500, 2.0, 6.0), rng.integers(0, n, 500), dst7))
+    jobs.append(("l2l", wl.random_shifts(rng, 250, 0.25, 0.5), np.arange(3000, 3250), np.arange(3500, 3750)))
+
+    def run(queued):
+        srv = sh.Server(ctx, pool_bytes=64 << 20, staging_bytes=8 << 20, streams=3, max_batch_jobs=16)
+        t, M, L = make_tree(srv, orc, sh.SH_F64, P, n, 21)
+        ids = []
+        for op, r, s, d in jobs:
+            ids.append(srv.submit(t, op, r, s, d))
+            if not queued:
+                srv.wait(ids.pop())
+        for i in ids:
+            srv.wait(i)
+        out, _ = read_pool(srv, t, 1, P, n, sh.SH_F64)
+        st = srv.stats()
+        srv.close()
+        return out, M, L, st
+
+    alone, M, L, _ = run(False)
+    mixed, _, _, st = run(True)
+    print(f"[server] one tree: {st['batches']} batches, mean jobs/batch {st['mean_batch_jobs']:.2f}", flush=True)
+    assert np.array_equal(alone, mixed)
+    exp = L.copy()
+    for op, r, s, d in jobs[:7]:
+        exp[d] = orc.translate_batch("m2l", P, P, r, M[s])
+    op, r, s, d = jobs[7]
+    exp[d] = orc.translate_batch("l2l", P, P, r, exp[s])
+    check(mixed, exp, P, "L", 4 * TOL[sh.SH_F64], "shared tree")
