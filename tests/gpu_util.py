@@ -97,6 +97,29 @@ def dense_operator(orc, op, p_in, p_out, r):
     return T * s_out[:, None] / s_in[None, :]
 
 
+def _bf16(x):
+    """Round float32 values to bfloat16 (round to nearest even), returned as float32."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def _split_bf16(x, pieces):
+    """x (float64 or float32) as a sum of `pieces` bfloat16 values, each rounded from the
+    remainder of the previous ones (the split of the matrix-core forms)."""
+    rest = np.asarray(x, np.float64)
+    out = []
+    for _ in range(pieces):
+        p = _bf16(rest.astype(np.float32))
+        out.append(p)
+        rest = rest - p.astype(np.float64)
+    return out
+
+
+# Products of the BF16 split forms: (operator piece, input piece) index pairs.
+BF16_PRODUCTS = {3: [(0, 0), (0, 1), (1, 0)], 6: [(0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0)]}
+
+
 class Plain32:
     """A plain FP32 evaluation of the same translations, as the reference for FP32 bounds.
 
@@ -105,22 +128,34 @@ class Plain32:
     (the FP64 oracle applied to unit solids, for the shift rounded to FP32, as the FP32 entry
     points receive it) and rounded once to FP32, the input is the FP32 normalised solid the GPU
     receives, and the products and sums are formed one by one in FP32 (each rounded, no
-    fused multiply-add), starting from the FP32 initial output for an accumulating call.  Its
-    per-degree error against the exact result measures what FP32 arithmetic costs on that
-    input: where a degree's coefficients cancel, every FP32 evaluation errs by a few rounding
-    units of sum_k |T_hat| |a_k| rather than of the result.
+    fused multiply-add), starting from the FP32 initial output for an accumulating call.
+
+    A plain dot product has no preferred summation order, and where a degree's coefficients
+    cancel the error of one order is a draw from a wide distribution: on one octree M2L at
+    P = 16 (shift (1, 2, 2)) eight orders gave 1.5e-6 .. 1.5e-5, and on one L2L at P = 9 with
+    |r| = 5.1, 5.5e-7 .. 9.4e-5.  error() is therefore the largest error over ORDERS summation
+    orders (the natural one, the reversed one and seeded permutations): the error FP32
+    arithmetic can make on that input, not one lucky draw.
+
+    bf16 = 3 or 6 evaluates the BF16 split forms instead: operator and input split into BF16
+    pieces (_split_bf16) and the listed piece products (exact in FP32) summed in FP32.
 
     apply(r_rows, C_rows) -> output rows is the oracle's operation (paper basis)."""
 
-    def __init__(self, apply, p_in, p_out, in_kind, out_kind, r, C, base=None):
+    ORDERS = 8
+
+    def __init__(self, apply, p_in, p_out, in_kind, out_kind, r, C, base=None, bf16=0):
         self.apply, self.p_in, self.p_out = apply, p_in, p_out
         self.in_kind, self.out_kind = in_kind, out_kind
         self.r = np.asarray(r, np.float32).astype(np.float64).reshape(-1, 3)
         self.C = np.asarray(C, np.float64).reshape(self.r.shape[0], -1)
         self.base = None if base is None else np.asarray(base, np.float64)
+        self.bf16 = bf16
         self._ops = {}
 
     def operator(self, r):
+        """The translation's dense operator in the normalised basis: FP32, or for the BF16
+        forms the list of its BF16 pieces."""
         key = tuple(r)
         if key not in self._ops:
             K = self.p_in * (self.p_in + 1)
@@ -128,23 +163,43 @@ class Plain32:
             w_in, w_out = weights_flat(self.p_in), weights_flat(self.p_out)
             s_in = w_in if self.in_kind == "M" else 1.0 / w_in
             s_out = w_out if self.out_kind == "M" else 1.0 / w_out
-            self._ops[key] = (T * s_out[:, None] / s_in[None, :]).astype(np.float32)
+            T = T * s_out[:, None] / s_in[None, :]
+            self._ops[key] = _split_bf16(T, 3) if self.bf16 else T.astype(np.float32)
         return self._ops[key]
 
-    def result(self, i):
-        """The plain FP32 evaluation of translation i (paper basis, FP64 array)."""
+    def _terms(self, i):
+        """Per input k, the FP32 contribution column (outputs x K) of translation i."""
         T = self.operator(self.r[i])
         a = to_basis(self.C[i, : self.p_in * (self.p_in + 1)], self.p_in, self.in_kind, sh.SH_F32)
+        if not self.bf16:
+            return T * a[None, :]
+        ap = _split_bf16(a, 3)
+        terms = np.zeros(T[0].shape, np.float32)
+        for ti, ai in BF16_PRODUCTS[self.bf16]:
+            terms = terms + T[ti] * ap[ai][None, :]  # each product exact, the sum rounded
+        return terms
+
+    def results(self, i):
+        """The evaluations of translation i in ORDERS summation orders (paper basis)."""
+        terms = self._terms(i)
+        K = terms.shape[1]
         if self.base is None:
-            y = np.zeros(T.shape[0], np.float32)
+            y0 = np.zeros(terms.shape[0], np.float32)
         else:
-            y = to_basis(self.base[i], self.p_out, self.out_kind, sh.SH_F32)
-        for k in range(T.shape[1]):
-            y = y + T[:, k] * a[k]
-        return from_basis(y, self.p_out, self.out_kind, sh.SH_F32)
+            y0 = to_basis(self.base[i], self.p_out, self.out_kind, sh.SH_F32)
+        rng = np.random.default_rng(1234 + i)
+        orders = [np.arange(K), np.arange(K)[::-1]] + [rng.permutation(K) for _ in range(self.ORDERS - 2)]
+        out = []
+        for perm in orders:
+            y = y0.copy()
+            for k in perm:
+                y = y + terms[:, k]
+            out.append(from_basis(y, self.p_out, self.out_kind, sh.SH_F32))
+        return out
 
     def error(self, i, ref_i):
-        return max_degree_error(self.result(i), ref_i, self.p_out, self.out_kind)
+        """Largest per-degree error of the plain evaluations of translation i against ref_i."""
+        return max(max_degree_error(y, ref_i, self.p_out, self.out_kind) for y in self.results(i))
 
 
 def plain32_for(orc, op, p_in, p_out, r, C, base=None):
@@ -153,8 +208,8 @@ def plain32_for(orc, op, p_in, p_out, r, C, base=None):
                    IN_KIND[op], OUT_KIND[op], r, C, base)
 
 
-# FP32 bound per translation: max(tol, PLAIN32_FACTOR x the error of the plain FP32 evaluation
-# of the same translation, Plain32).  FP32 results of the rotation path, of the FP64-arithmetic
+# FP32 bound per translation: max(tol, PLAIN32_FACTOR x the error of plain FP32 evaluations of
+# the same translation, Plain32).  FP32 results of the rotation path, of the FP64-arithmetic
 # path at high orders and of the matrix-core forms all round at different places than the plain
 # dot products; a factor 2 allows for that and nothing more.
 PLAIN32_FACTOR = 2.0
