@@ -342,6 +342,23 @@ sh_status sh_m2m_f32(const sh_ctx *ctx, int p_in, int p_out, const float r[3],
 sh_status sh_l2l_f32(const sh_ctx *ctx, int p_in, int p_out, const float r[3],
                      const float *L, float *Lout);
 
+/* ---------------- single translation without allocation ----------------
+ * For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc): the single host-pointer translation above, for any op and dtype
+ * (r: 3 reals; in: p_in(p_in+1) reals; out: p_out(p_out+1) reals, all host memory of the
+ * dtype), staged through a fixed device array of SH_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU until the process ends, instead of a per-call hipMalloc.
+ * Calls no hipMalloc / hipFree.  Same kernel, same layout and same result bits as
+ * sh_m2l_f64 ... sh_l2l_f32.  Synchronous; the array keeps the last call's contents.
+ * Calls on one GPU share the array: the library serialises them within a process (a
+ * second host thread waits for the first).  The array is resolved per device by
+ * sh_create, so a context for the device must exist.  Errors: as the single calls, plus
+ * SH_EBUSY if the staging (3 + p_in(p_in+1) + p_out(p_out+1) reals) exceeds the array
+ * (never for orders <= SH_MAX_ORDER), SH_EINVAL for an unknown op or dtype. */
+#define SH_NOALLOC_SCRATCH_BYTES 66816
+sh_status sh_translate_single_noalloc(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out,
+                                      const void *r, const void *in, void *out);
+
 /* ---------------- baseline and neighbouring steps ----------------
  * Direct double-height M2L (eq. m2lkernels, right) with S by the Appendix recurrence:
  * the O(P^4) loop the paper benchmarks against (Section 4), FP64, same layout and

@@ -31,6 +31,7 @@ SH_SHARED_FP32 = 1
 SH_SHARED_BF16X3 = 3
 SH_SHARED_BF16X6 = 6
 SH_MAX_ORDER = 64
+SH_NOALLOC_SCRATCH_BYTES = 66816  # staging array of sh_translate_single_noalloc
 OPS = {"m2m": SH_M2M, "m2l": SH_M2L, "l2l": SH_L2L}
 
 
@@ -87,6 +88,7 @@ _SIGS = {
     "sh_server_wait": (_c_i32, [_vp, _c_i64, ctypes.POINTER(ctypes.c_double)]),
     "sh_server_drain": (_c_i32, [_vp]),
     "sh_server_stats_get": (_c_i32, [_vp, _vp]),
+    "sh_translate_single_noalloc": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp]),
 }
 for _op in ("m2l", "m2m", "l2l"):
     for _dt in ("f64", "f32"):
@@ -249,6 +251,18 @@ for _op in ("m2l", "m2m", "l2l"):
         globals()[f"sh_{_op}_batch_{_dt}"] = _make_batch(f"sh_{_op}_batch_{_dt}")
         globals()[f"sh_{_op}_{_dt}"] = _make_single(f"sh_{_op}_{_dt}", _npdt)
 sh_m2l_naive_batch_f64 = _make_batch("sh_m2l_naive_batch_f64")
+
+
+def sh_translate_single_noalloc(ctx, op, dtype, p_in, p_out, r, C):
+    """Single translation on host arrays through the library's fixed staging array (no
+    device allocation); returns the output solid."""
+    npdt = np.float64 if dtype == SH_F64 else np.float32
+    r = np.ascontiguousarray(r, dtype=npdt)
+    C = np.ascontiguousarray(C, dtype=npdt)
+    out = np.zeros(p_out * (p_out + 1), npdt)
+    _check(lib().sh_translate_single_noalloc(_h(ctx), OPS.get(op, op), dtype, p_in, p_out, r.ctypes.data,
+                                             C.ctypes.data, out.ctypes.data), "sh_translate_single_noalloc")
+    return out
 
 
 def sh_p2m_batch_f64(ctx, P, count, centres, npts, pts, q, M, ldM, stream=None):

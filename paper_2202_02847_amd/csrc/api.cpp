@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -80,20 +82,32 @@ sh_status launch(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int6
     return e == hipSuccess ? SH_OK : SH_EDEVICE;
 }
 
-template <typename Real>
-sh_status single(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, const Real r[3],
-                 const Real *C, Real *out)
+// Checks the arguments of a single host-pointer translation (shared by the allocating
+// calls and sh_translate_single_noalloc).
+sh_status single_check(const sh_ctx *ctx, int op, int p_in, int p_out, double x, double y, double z)
 {
-    if (!ctx || !r || !C || !out) return SH_EINVAL;
     if (p_in < 1 || p_out < 1 || p_in > ctx->max_order || p_out > ctx->max_order) return SH_EORDER;
-    const double x = r[0], y = r[1], z = r[2];
     if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return SH_ESHIFT;
     if (op == SH_M2L && x == 0 && y == 0 && z == 0) return SH_ESHIFT;
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return SH_EDEVICE;
+    return SH_OK;
+}
+
+// Reals of device staging a single translation uses: the shift, then the input solid,
+// then the output solid, back to back.
+size_t single_staging_reals(int p_in, int p_out)
+{
+    return 3 + (size_t)p_in * (p_in + 1) + (size_t)p_out * (p_out + 1);
+}
+
+// One translation staged through device memory d (single_staging_reals reals): copy the
+// shift and the input in, run the batched path on the null stream, copy the output back.
+// The allocating calls and the no-allocation call run exactly this, so they launch the
+// same kernel on the same layout and return the same bits.
+template <typename Real>
+sh_status single_staged(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, const Real *r,
+                        const Real *C, Real *out, Real *d)
+{
     const size_t nin = (size_t)p_in * (p_in + 1), nout = (size_t)p_out * (p_out + 1);
-    Real *d = nullptr;
-    if (hipMalloc(&d, sizeof(Real) * (3 + nin + nout)) != hipSuccess) return SH_ENOMEM;
     sh_status st = SH_OK;
     if (hipMemcpy(d, r, 3 * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d + 3, C, nin * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess)
@@ -103,8 +117,61 @@ sh_status single(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, cons
                     d + 3 + nin, (int64_t)nout, 0, nullptr);
     if (st == SH_OK && hipMemcpy(out, d + 3 + nin, nout * sizeof(Real), hipMemcpyDeviceToHost) != hipSuccess)
         st = SH_EDEVICE;
+    return st;
+}
+
+template <typename Real>
+sh_status single(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, const Real r[3],
+                 const Real *C, Real *out)
+{
+    if (!ctx || !r || !C || !out) return SH_EINVAL;
+    sh_status st = single_check(ctx, op, p_in, p_out, r[0], r[1], r[2]);
+    if (st != SH_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return SH_EDEVICE;
+    Real *d = nullptr;
+    if (hipMalloc(&d, sizeof(Real) * single_staging_reals(p_in, p_out)) != hipSuccess) return SH_ENOMEM;
+    st = single_staged(ctx, op, dtype, p_in, p_out, r, C, out, d);
     (void)hipFree(d);
     return st;
+}
+
+// ---- staging of sh_translate_single_noalloc ----
+// One array per GPU for the life of the process, sized for two solids of order
+// SH_MAX_ORDER plus a shift in FP64.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels and copies use the address hipGetSymbolAddress returns,
+// taken once per device when the first context on that device is created.
+static_assert(SH_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static_assert(SH_NOALLOC_SCRATCH_BYTES >= (3 + 2 * SH_MAX_ORDER * (SH_MAX_ORDER + 1)) * sizeof(double),
+              "scratch holds a shift and two solids of the highest order in FP64");
+static __device__ __align__(256) double scratch[SH_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+struct NoallocSlot {
+    void *ptr = nullptr;  // device address of this GPU's `scratch`
+    std::mutex mu;        // one call at a time per GPU within the process
+};
+
+std::mutex g_noalloc_mu;
+std::map<int, std::unique_ptr<NoallocSlot>> g_noalloc;
+
+// Resolves `scratch` on `device` (current) once; later calls find the stored address.
+hipError_t noalloc_setup(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto &slot = g_noalloc[device];
+    if (!slot) slot.reset(new NoallocSlot);
+    if (slot->ptr) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) slot->ptr = p;
+    return e;
+}
+
+NoallocSlot *noalloc_slot(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(device);
+    return (it == g_noalloc.end() || !it->second->ptr) ? nullptr : it->second.get();
 }
 
 long double weight(int n, int m)
@@ -181,6 +248,8 @@ sh_status sh_create(sh_ctx **out, int max_order, int device)
         shfmm::build_tables(shfmm::kMaxOrder, ht);
         DeviceGuard g(device);
         if (!g.ok) return SH_EDEVICE;
+        // the staging of sh_translate_single_noalloc on this device (resolved once)
+        if (noalloc_setup(device) != hipSuccess) return SH_EDEVICE;
         // layout: swap64[4] | z64[3] | swap32[4] | z32[3] | swap64n[4] | z64n[3] | err flag,
         // each 256-byte aligned
         auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -361,6 +430,36 @@ SH_SINGLE(sh_m2l_f32, SH_M2L, SH_F32, float)
 SH_SINGLE(sh_m2m_f32, SH_M2M, SH_F32, float)
 SH_SINGLE(sh_l2l_f32, SH_L2L, SH_F32, float)
 #undef SH_SINGLE
+
+sh_status sh_translate_single_noalloc(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, const void *r,
+                                      const void *in, void *out)
+{
+    try {
+        if (!ctx || !r || !in || !out || !valid_op(op) || !valid_dtype(dtype)) return SH_EINVAL;
+        const bool f64 = dtype == SH_F64;
+        const double x = f64 ? static_cast<const double *>(r)[0] : static_cast<const float *>(r)[0];
+        const double y = f64 ? static_cast<const double *>(r)[1] : static_cast<const float *>(r)[1];
+        const double z = f64 ? static_cast<const double *>(r)[2] : static_cast<const float *>(r)[2];
+        sh_status st = single_check(ctx, op, p_in, p_out, x, y, z);
+        if (st != SH_OK) return st;
+        const size_t bytes = single_staging_reals(p_in, p_out) * (f64 ? sizeof(double) : sizeof(float));
+        if (bytes > SH_NOALLOC_SCRATCH_BYTES) return SH_EBUSY;
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return SH_EDEVICE;
+        NoallocSlot *slot = noalloc_slot(ctx->device);
+        if (!slot) return SH_EDEVICE;
+        std::lock_guard<std::mutex> lk(slot->mu);
+        if (f64)
+            return single_staged(ctx, op, dtype, p_in, p_out, static_cast<const double *>(r),
+                                 static_cast<const double *>(in), static_cast<double *>(out),
+                                 static_cast<double *>(slot->ptr));
+        return single_staged(ctx, op, dtype, p_in, p_out, static_cast<const float *>(r),
+                             static_cast<const float *>(in), static_cast<float *>(out),
+                             static_cast<float *>(slot->ptr));
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
 
 sh_status sh_m2l_naive_batch_f64(const sh_ctx *ctx, int p_in, int p_out, int64_t count, const double *r,
                                  const double *in, int64_t ld_in, double *out, int64_t ld_out,
