@@ -262,8 +262,12 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
 
     Then a saturation leg: `sat_jobs` jobs of the same distribution queued at once (closed
     loop), through a new server with a staging budget 8x larger, against the same job stream
-    issued as plain calls: one indexed batched call per job on one stream, its shift and slot
-    arrays copied from pinned host memory before each call."""
+    issued as plain calls: per job, its shift and slot arrays copied from the same host arrays
+    to the device and one indexed batched call, on one stream.  Both legs are timed from the
+    first submission (call) to the last completion; submit_s is the served leg's submission
+    loop (validation and packing on the submitting thread).  plain_device_resident_s times the
+    same calls with the job arrays already on the device (their transfer not timed): the plain
+    path's device-side lower bound."""
     pool = sum(2 * n_slots * P * (P + 1) * (8 if dt == sh.SH_F64 else 4) for P in SERVE_ORDERS
                for dt in (sh.SH_F64, sh.SH_F32))
     srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=staging, streams=4, max_batch_jobs=64)
@@ -297,7 +301,9 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
     sat_staging = 8 * staging
     srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=sat_staging, streams=4, max_batch_jobs=64)
     trees = _serving_trees(sh, srv, n_slots)
+    t0 = time.perf_counter()
     ids = [srv.submit(trees[(P, dt)], op, r, src, dst) for P, dt, op, r, src, dst in jobs]
+    t_submit = time.perf_counter() - t0
     srv.drain()
     for i in ids:
         srv.wait(i)
@@ -310,28 +316,47 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
         for dt in (sh.SH_F64, sh.SH_F32):
             tdt = torch.float64 if dt == sh.SH_F64 else torch.float32
             pools[(P, dt)] = [torch.full((n_slots, P * (P + 1)), 1e-2, dtype=tdt, device=dev) for _ in range(2)]
-    staged = []
-    for P, dt, op, r, src, dst in jobs:
-        npdt = np.float64 if dt == sh.SH_F64 else np.float32
-        staged.append((P, dt, op, len(src), torch.from_numpy(r.astype(npdt)).pin_memory(),
-                       torch.from_numpy(src.astype(np.int64)).pin_memory(),
-                       torch.from_numpy(dst.astype(np.int64)).pin_memory()))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for P, dt, op, count, r, src, dst in staged:
-        d_r, d_s, d_d = (x.to(dev, non_blocking=True) for x in (r, src, dst))
+    for P, dt, op, r, src, dst in jobs:
+        # the job as the server receives it: host arrays, shifts converted to the pool's dtype
+        npdt = np.float64 if dt == sh.SH_F64 else np.float32
+        d_r = torch.from_numpy(np.ascontiguousarray(r, npdt)).to(dev, non_blocking=True)
+        d_s = torch.from_numpy(np.ascontiguousarray(src, np.int64)).to(dev, non_blocking=True)
+        d_d = torch.from_numpy(np.ascontiguousarray(dst, np.int64)).to(dev, non_blocking=True)
+        Mp, Lp = pools[(P, dt)]
+        S = P * (P + 1)
+        inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
+        sh.sh_translate_indexed(ctx, op, dt, P, P, len(src), d_r, d_s, inp, S, d_d, out, S)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # the same calls with every job's arrays already on the device (their transfer not timed):
+    # the device-side lower bound of the plain path
+    dev_jobs = []
+    for P, dt, op, r, src, dst in jobs:
+        npdt = np.float64 if dt == sh.SH_F64 else np.float32
+        dev_jobs.append((P, dt, op, len(src), torch.from_numpy(np.ascontiguousarray(r, npdt)).to(dev),
+                         torch.from_numpy(np.ascontiguousarray(src, np.int64)).to(dev),
+                         torch.from_numpy(np.ascontiguousarray(dst, np.int64)).to(dev)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for P, dt, op, count, d_r, d_s, d_d in dev_jobs:
         Mp, Lp = pools[(P, dt)]
         S = P * (P + 1)
         inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
         sh.sh_translate_indexed(ctx, op, dt, P, P, count, d_r, d_s, inp, S, d_d, out, S)
     torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    t_resident = time.perf_counter() - t0
+    del dev_jobs
     ntr = sum(len(j[4]) for j in jobs)
+    sat["plain_device_resident_s"] = round(t_resident, 4)
+    sat["served_over_plain_device_resident"] = round(t_resident / max(sat["duration_s"], 1e-9), 3)
+    sat["submit_s"] = round(t_submit, 4)
     sat["plain_translations_per_s"] = ntr / t_plain
     sat["plain_s"] = round(t_plain, 4)
     sat["served_over_plain"] = round(sat["translations_per_s"] / sat["plain_translations_per_s"], 3)
     res["saturation"] = sat
-    del pools, staged
+    del pools
     torch.cuda.empty_cache()
     return res
 
@@ -519,6 +544,40 @@ def run_counters(sh, ctx, torch, dev, what, steps):
     log(f"[counters] done: copy 1 GiB + {steps} x {what}")
 
 
+def run_section(sh, ctx, torch, dev, name, args):
+    """One extra section of the bench (returns its entries of the `extra` object)."""
+    out = {}
+    if name == "serving":
+        log("[bench] serving")
+        out["serving"] = run_serving(sh, ctx, torch, dev, seconds=args.serve_seconds)
+    elif name == "precision":
+        log("[bench] shared-direction precision forms P=16")
+        out["precision_p16"] = run_precision(sh, ctx, torch, dev)
+    elif name == "mixed":
+        for dt, dname in ((sh.SH_F64, "f64"), (sh.SH_F32, "f32")):
+            log(f"[bench] mixed-order list {dname}")
+            out[f"mixed_list_{dname}"] = run_mixed(sh, ctx, torch, dev, dt)
+            torch.cuda.empty_cache()
+    elif name == "fmm":
+        log("[bench] FMM P=10 262144 particles")
+        out["fmm_p10_uniform_262k"] = run_fmm(sh, ctx, torch, dev)
+    elif name == "l2p":
+        log("[bench] L2P P=10")
+        out["l2p_p10_f64"] = run_l2p(sh, ctx, torch, dev)
+    elif name == "orders":
+        for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
+            log(f"[bench] extra P={PP} n={nn_}")
+            J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)
+            SS = solid(PP)
+            d_out = torch.empty((nn_, SS), dtype=torch.float64, device=dev)
+            t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, PP, PP, nn_, J["r"], J["M"], SS, d_out, SS), 3)
+            out[f"m2l_p{PP}_f64_per_s"] = nn_ / t
+            out[f"m2l_p{PP}_f64_frac_hbm"] = bytes_per_translation(PP, PP, 8) * nn_ / t / 1e9 / HBM_PEAK_GBS
+            del J, d_out
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -534,6 +593,8 @@ def main():
                          "FETCH_SIZE/WRITE_SIZE scaling), then --steps launches of one workload "
                          "(P or m2l:P, m2l32:P, shared6:P, shared3:P, sharedf32:P, mixed64, mixed32, "
                          "fmm), nothing else; prints no JSON line")
+    ap.add_argument("--only", default="", choices=["", "serving", "precision", "mixed", "fmm", "l2p", "orders"],
+                    help="run one extra section alone and print its JSON (no headline line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -547,6 +608,9 @@ def main():
     ctx = sh.Context(max_order=32, device=0)
     if args.counters:
         run_counters(sh, ctx, torch, dev, args.counters, args.steps)
+        return
+    if args.only:
+        print(json.dumps({"only": args.only, "extra": run_section(sh, ctx, torch, dev, args.only, args)}), flush=True)
         return
     P, n, nc = 10, 1 << 20, 1 << 17
     log(f"[bench] generating octree inputs P={P} n={n}")
@@ -623,31 +687,8 @@ def main():
         extra["m2l_p10_naive_f64_per_s"] = nv / t
         del d_M, d_L, d_M2, d_L2, I
         torch.cuda.empty_cache()
-        log("[bench] serving")
-        extra["serving"] = run_serving(sh, ctx, torch, dev, seconds=args.serve_seconds)
-        torch.cuda.empty_cache()
-        log("[bench] shared-direction precision forms P=16")
-        extra["precision_p16"] = run_precision(sh, ctx, torch, dev)
-        torch.cuda.empty_cache()
-        for dt, name in ((sh.SH_F64, "f64"), (sh.SH_F32, "f32")):
-            log(f"[bench] mixed-order list {name}")
-            extra[f"mixed_list_{name}"] = run_mixed(sh, ctx, torch, dev, dt)
-            torch.cuda.empty_cache()
-        log("[bench] FMM P=10 262144 particles")
-        extra["fmm_p10_uniform_262k"] = run_fmm(sh, ctx, torch, dev)
-        torch.cuda.empty_cache()
-        log("[bench] L2P P=10")
-        extra["l2p_p10_f64"] = run_l2p(sh, ctx, torch, dev)
-        torch.cuda.empty_cache()
-        for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
-            log(f"[bench] extra P={PP} n={nn_}")
-            J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)
-            SS = solid(PP)
-            d_out = torch.empty((nn_, SS), dtype=torch.float64, device=dev)
-            t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, PP, PP, nn_, J["r"], J["M"], SS, d_out, SS), 3)
-            extra[f"m2l_p{PP}_f64_per_s"] = nn_ / t
-            extra[f"m2l_p{PP}_f64_frac_hbm"] = bytes_per_translation(PP, PP, 8) * nn_ / t / 1e9 / HBM_PEAK_GBS
-            del J, d_out
+        for name in ("serving", "precision", "mixed", "fmm", "l2p", "orders"):
+            extra.update(run_section(sh, ctx, torch, dev, name, args))
             torch.cuda.empty_cache()
 
     line = {"metric": METRIC, "value": value, "unit": "translations/s", "n_gpus": 1, "steps": args.steps,

@@ -257,9 +257,10 @@ void sh_shared_destroy(sh_shared *shared);
  * the staging arena has room and nothing in flight on their tree conflicts: overwriting M2L
  * jobs (no SH_ACCUMULATE) share a tree while their destination slots are disjoint, M2M, L2L
  * and accumulating jobs run alone on their tree, and a job passed over holds back every later
- * job of its tree.  Every admissible job joins the next batch, which runs as one mixed work
- * list per (dtype, accumulate) group on the least loaded stream, so batches overlap on the
- * device.  A translation's result does not depend on the batch it ran in.
+ * job of its tree.  Every admissible job joins the next batch, which runs as one indexed
+ * translation call per (dtype, operation, orders, accumulate) group -- jobs of different
+ * trees share a call -- on the least loaded stream, so batches overlap on the device.  A
+ * translation's result does not depend on the batch it ran in.
  * Thread safety: every call may come from any host thread. */
 typedef struct sh_server sh_server;
 

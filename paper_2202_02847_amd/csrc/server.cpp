@@ -11,8 +11,8 @@
 //   on their tree.  A job passed over keeps every later job of its tree waiting, so jobs that
 //   touch the same slots complete in submission order.
 // * Continuous batching.  The scheduler thread fuses every admissible job into one batch:
-//   one mixed work list per (dtype, accumulate) group, binned and launched like a plan, on
-//   the least loaded of a few streams, so batches overlap on the device and jobs arriving
+//   one indexed translation call per (dtype, operation, orders, accumulate) group, on the
+//   least loaded of a few streams, so batches overlap on the device and jobs arriving
 //   meanwhile join the next batch as soon as staging frees up.
 // * Latency.  One completion thread per stream waits for its batches in order and stamps
 //   every job of a finished batch; p50 / p99 are taken over all completed jobs.
@@ -34,12 +34,8 @@
 
 #include "context.hpp"
 #include "kernels.hpp"
-#include "list_plan.hpp"
 
 using shfmm::DeviceGuard;
-using shfmm::ListBin;
-using shfmm::ListItem;
-using shfmm::ListTask;
 
 namespace {
 
@@ -99,7 +95,8 @@ struct Tree {
     int dtype = SH_F64;
     int p_m = 0, p_l = 0;
     int64_t n_m = 0, n_l = 0;
-    int64_t off_m = 0, off_l = 0;  // byte offsets in the pool arena
+    int64_t off_m = 0, off_l = 0;  // byte offsets of the pools in the arena (multiples of a solid)
+    int64_t raw_m = 0, raw_l = 0;  // the allocated ranges (offset, length) they sit in
     int64_t bytes_m = 0, bytes_l = 0;
     int running = 0;               // jobs of this tree reserved for a batch or in flight
     bool exclusive = false;        // one of them needs the tree alone
@@ -114,8 +111,12 @@ bool shares_tree(int op, unsigned flags) { return op == SH_M2L && !(flags & SH_A
 struct Job {
     int32_t tree = 0, op = 0;
     unsigned flags = 0;
-    std::vector<double> r;
-    std::vector<int64_t> src, dst;
+    int64_t count = 0;
+    std::vector<int64_t> dst;   // destination slots (claims of shared trees)
+    // packed at submission in the layout a batch stages: the shifts in the tree's dtype
+    // (count x 3), then the source and the destination slots as solid indices counted from
+    // the start of the pool arena (count each)
+    std::vector<char> packed;
     int64_t footprint = 0;
     double t_submit = 0, t_done = 0;
     bool done = false;
@@ -174,36 +175,6 @@ struct sh_server {
 
 namespace {
 
-// Appends one job's work records to the per-(dtype, accumulate) lists.
-void job_items(const Tree &t, const Job &j, std::vector<ListItem> &out)
-{
-    const int64_t elem = t.dtype == SH_F32 ? 4 : 8;
-    const int64_t sm = (int64_t)t.p_m * (t.p_m + 1), sl = (int64_t)t.p_l * (t.p_l + 1);
-    int64_t in_base, out_base, s_in, s_out;
-    int p_in, p_out;
-    if (j.op == SH_M2L) {
-        in_base = t.off_m / elem; s_in = sm; p_in = t.p_m;
-        out_base = t.off_l / elem; s_out = sl; p_out = t.p_l;
-    } else if (j.op == SH_M2M) {
-        in_base = out_base = t.off_m / elem; s_in = s_out = sm; p_in = p_out = t.p_m;
-    } else {
-        in_base = out_base = t.off_l / elem; s_in = s_out = sl; p_in = p_out = t.p_l;
-    }
-    const size_t n = j.src.size();
-    for (size_t i = 0; i < n; ++i) {
-        ListItem it{};
-        it.op = j.op;
-        it.p_in = p_in;
-        it.p_out = p_out;
-        it.in_off = in_base + j.src[i] * s_in;
-        it.out_off = out_base + j.dst[i] * s_out;
-        it.r[0] = j.r[3 * i];
-        it.r[1] = j.r[3 * i + 1];
-        it.r[2] = j.r[3 * i + 2];
-        out.push_back(it);
-    }
-}
-
 // Reserves (on) or releases (off) a job's claim on its tree: the running count, the tree
 // alone for a job that does not share it, the destination slots for one that does.  Called
 // with the server lock held.
@@ -218,60 +189,71 @@ void reserve_job(Tree &t, const Job &j, bool on)
 }
 
 // Builds and launches one batch (called by the scheduler without the lock; the batch's jobs
-// and trees are reserved, so nothing it reads changes meanwhile).
+// and trees are reserved, so nothing it reads changes meanwhile).  The batch's jobs are grouped
+// by (dtype, operation, orders, accumulate); each group runs as one indexed translation call
+// whose slot indices count solids from the start of the pool arena (every pool sits at a
+// multiple of its solid size), so jobs of different trees share the call.  Staging per group:
+// the shifts (in the group's dtype), then the source and the destination indices, each run
+// 256-byte aligned.  The kernel a translation runs on follows from its own operation and
+// orders, never from its batch mates.
 hipError_t launch_batch(sh_server *S, Batch &b)
 {
-    // groups: (dtype, accumulate)
-    std::vector<ListItem> items[2][2];
-    for (size_t k = 0; k < b.jp.size(); ++k) {
-        const Job &j = *b.jp[k];
-        const int dt = b.tp[k]->dtype;
-        job_items(*b.tp[k], j, items[dt][(j.flags & SH_ACCUMULATE) ? 1 : 0]);
-    }
     struct Group {
-        int dtype;
+        int dtype, op, p_in, p_out;
         unsigned flags;
-        std::vector<ListItem> items;
-        std::vector<ListTask> tasks;
-        std::vector<ListBin> bins;
-        int64_t item_off = 0, task_off = 0;
+        std::vector<size_t> jobs;  // indices into b.jp
+        int64_t count = 0, r_off = 0, s_off = 0, d_off = 0;
     };
     std::vector<Group> groups;
-    int64_t bytes = 0;
-    for (int dt = 0; dt < 2; ++dt)
-        for (int acc = 0; acc < 2; ++acc) {
-            if (items[dt][acc].empty()) continue;
-            Group g;
-            g.dtype = dt;
-            g.flags = acc ? SH_ACCUMULATE : 0;
-            g.items.swap(items[dt][acc]);
-            // a fixed mapping: the kernel a translation runs on follows from its own operation
-            // and orders, never from the other jobs of the batch
-            auto choose = [](ListBin &, const std::vector<ListItem> &) { return (int)shfmm::MAP_LPT64; };
-            if (shfmm::bin_items(dt, g.items, g.tasks, g.bins, choose) != SH_OK) return hipErrorUnknown;
-            g.item_off = bytes;
-            bytes = round_up(bytes + (int64_t)(g.items.size() * sizeof(ListItem)));
-            g.task_off = bytes;
-            bytes = round_up(bytes + (int64_t)(g.tasks.size() * sizeof(ListTask)));
-            groups.push_back(std::move(g));
+    for (size_t k = 0; k < b.jp.size(); ++k) {
+        const Job &j = *b.jp[k];
+        const Tree &t = *b.tp[k];
+        const int p_in = j.op == SH_L2L ? t.p_l : t.p_m, p_out = j.op == SH_M2M ? t.p_m : t.p_l;
+        const unsigned fl = j.flags & SH_ACCUMULATE;
+        Group *g = nullptr;
+        for (auto &x : groups)
+            if (x.dtype == t.dtype && x.op == j.op && x.p_in == p_in && x.p_out == p_out && x.flags == fl) g = &x;
+        if (!g) {
+            groups.push_back(Group{t.dtype, j.op, p_in, p_out, fl, {}});
+            g = &groups.back();
         }
+        g->jobs.push_back(k);
+        g->count += j.count;
+    }
+    int64_t bytes = 0;
+    for (auto &g : groups) {
+        const int64_t elem = g.dtype == SH_F32 ? 4 : 8;
+        g.r_off = bytes;
+        bytes = round_up(bytes + 3 * elem * g.count);
+        g.s_off = bytes;
+        bytes = round_up(bytes + 8 * g.count);
+        g.d_off = bytes;
+        bytes = round_up(bytes + 8 * g.count);
+    }
     if (bytes > b.st_bytes) return hipErrorInvalidValue;  // footprint bound violated (cannot happen)
     char *h = static_cast<char *>(S->hstage) + b.st_off;
     char *d = static_cast<char *>(S->dstage) + b.st_off;
     for (auto &g : groups) {
-        std::memcpy(h + g.item_off, g.items.data(), g.items.size() * sizeof(ListItem));
-        if (!g.tasks.empty()) std::memcpy(h + g.task_off, g.tasks.data(), g.tasks.size() * sizeof(ListTask));
+        const int64_t elem = g.dtype == SH_F32 ? 4 : 8;
+        int64_t at = 0;
+        for (size_t k : g.jobs) {
+            const Job &j = *b.jp[k];
+            const size_t rb = (size_t)(3 * elem * j.count), ib = (size_t)(8 * j.count);
+            std::memcpy(h + g.r_off + 3 * elem * at, j.packed.data(), rb);
+            std::memcpy(h + g.s_off + 8 * at, j.packed.data() + rb, ib);
+            std::memcpy(h + g.d_off + 8 * at, j.packed.data() + rb + ib, ib);
+            at += j.count;
+        }
     }
     hipStream_t s = S->streams[b.stream];
     hipError_t e = hipMemcpyAsync(d, h, (size_t)bytes, hipMemcpyHostToDevice, s);
     for (auto &g : groups) {
-        const bool f32 = g.dtype == SH_F32;
-        const ListItem *di = reinterpret_cast<const ListItem *>(d + g.item_off);
-        const ListTask *dtk = reinterpret_cast<const ListTask *>(d + g.task_off);
-        for (const ListBin &bin : g.bins) {
-            if (e != hipSuccess) break;
-            e = shfmm::launch_list_bin(S->ctx, f32, bin, di, dtk, S->pool, S->pool, g.flags, s);
-        }
+        if (e != hipSuccess) break;
+        const int64_t ld_in = (int64_t)g.p_in * (g.p_in + 1), ld_out = (int64_t)g.p_out * (g.p_out + 1);
+        const sh_status st = shfmm::translate_device(
+            S->ctx, g.op, g.dtype, g.p_in, g.p_out, g.count, d + g.r_off, reinterpret_cast<const int64_t *>(d + g.s_off),
+            S->pool, ld_in, reinterpret_cast<const int64_t *>(d + g.d_off), S->pool, ld_out, g.flags, s);
+        if (st != SH_OK) e = hipErrorUnknown;
     }
     if (e == hipSuccess) e = hipEventRecord(b.ev, s);
     return e;
@@ -350,7 +332,7 @@ void scheduler_main(sh_server *S)
                         Tree &t = S->trees.at(j->tree);
                         b.jp.push_back(j);
                         b.tp.push_back(&t);
-                        b.translations += (int64_t)j->src.size();
+                        b.translations += j->count;
                     }
                 }
             }
@@ -407,7 +389,7 @@ void completer_main(sh_server *S, int stream)
             if (j.status == SH_OK) {
                 S->latencies.push_back(t - j.t_submit);
                 ++S->jobs_done;
-                S->translations_done += (int64_t)j.src.size();
+                S->translations_done += j.count;
             } else {
                 ++S->failed;
             }
@@ -527,16 +509,22 @@ sh_status sh_server_tree_create(sh_server *S, int dtype, int p_m, int64_t n_m, i
         t.p_l = p_l;
         t.n_m = n_m;
         t.n_l = n_l;
-        t.bytes_m = std::max<int64_t>(kAlign, n_m * p_m * (p_m + 1) * elem);
-        t.bytes_l = std::max<int64_t>(kAlign, n_l * p_l * (p_l + 1) * elem);
+        // each pool starts at a multiple of its solid size in the arena, so that batches can
+        // address every tree's slots by solid index from the arena's start; the allocation
+        // holds one solid of slack for that
+        const int64_t sz_m = (int64_t)p_m * (p_m + 1) * elem, sz_l = (int64_t)p_l * (p_l + 1) * elem;
+        t.bytes_m = std::max<int64_t>(kAlign, (n_m + 1) * sz_m);
+        t.bytes_l = std::max<int64_t>(kAlign, (n_l + 1) * sz_l);
         std::lock_guard<std::mutex> lk(S->mu);
-        t.off_m = S->pool_alloc.alloc(t.bytes_m);
-        if (t.off_m < 0) return SH_EBUSY;
-        t.off_l = S->pool_alloc.alloc(t.bytes_l);
-        if (t.off_l < 0) {
-            S->pool_alloc.release(t.off_m, t.bytes_m);
+        t.raw_m = S->pool_alloc.alloc(t.bytes_m);
+        if (t.raw_m < 0) return SH_EBUSY;
+        t.raw_l = S->pool_alloc.alloc(t.bytes_l);
+        if (t.raw_l < 0) {
+            S->pool_alloc.release(t.raw_m, t.bytes_m);
             return SH_EBUSY;
         }
+        t.off_m = (t.raw_m + sz_m - 1) / sz_m * sz_m;
+        t.off_l = (t.raw_l + sz_l - 1) / sz_l * sz_l;
         const int32_t id = S->next_tree++;
         S->trees[id] = t;
         *tree = id;
@@ -593,8 +581,8 @@ sh_status sh_server_tree_destroy(sh_server *S, int32_t tree)
         wait_tree_idle(S, lk, tree);
         auto it = S->trees.find(tree);
         if (it == S->trees.end()) return SH_EINVAL;
-        S->pool_alloc.release(it->second.off_m, it->second.bytes_m);
-        S->pool_alloc.release(it->second.off_l, it->second.bytes_l);
+        S->pool_alloc.release(it->second.raw_m, it->second.bytes_m);
+        S->pool_alloc.release(it->second.raw_l, it->second.bytes_l);
         S->trees.erase(it);
         return SH_OK;
     } catch (...) {
@@ -613,39 +601,71 @@ sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
         j.tree = job->tree;
         j.op = job->op;
         j.flags = job->flags;
+        j.count = job->count;
         const size_t n = (size_t)job->count;
-        j.r.assign(job->r, job->r + 3 * n);
-        j.src.assign(job->src, job->src + n);
-        j.dst.assign(job->dst, job->dst + n);
         j.footprint = job_footprint(job->count);
-        for (size_t i = 0; i < n; ++i) {
-            const double *r = &j.r[3 * i];
-            if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2])) return SH_ESHIFT;
-            if (j.op == SH_M2L && r[0] == 0 && r[1] == 0 && r[2] == 0) return SH_ESHIFT;
-        }
-        int64_t n_in, n_out;
+        struct {
+            int dtype, p_m, p_l;
+            int64_t n_m, n_l, off_m, off_l;
+        } t;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             auto it = S->trees.find(j.tree);
             if (it == S->trees.end()) return SH_EINVAL;
-            n_in = j.op == SH_L2L ? it->second.n_l : it->second.n_m;
-            n_out = j.op == SH_M2M ? it->second.n_m : it->second.n_l;
+            const Tree &tr = it->second;
+            t = {tr.dtype, tr.p_m, tr.p_l, tr.n_m, tr.n_l, tr.off_m, tr.off_l};
         }
-        for (size_t i = 0; i < n; ++i)
-            if (j.src[i] < 0 || j.src[i] >= n_in || j.dst[i] < 0 || j.dst[i] >= n_out) return SH_EINVAL;
-        // destinations unique within the job; for M2M / L2L (one pool) no destination is also
-        // a source (one byte per slot of the destination pool)
-        std::vector<unsigned char> mark((size_t)n_out, 0);
-        for (int64_t d : j.dst) {
-            if (mark[(size_t)d]) return SH_EINVAL;
-            mark[(size_t)d] = 1;
+        const int64_t n_in = j.op == SH_L2L ? t.n_l : t.n_m;
+        const int64_t n_out = j.op == SH_M2M ? t.n_m : t.n_l;
+        const bool f32 = t.dtype == SH_F32;
+        const int64_t elem = f32 ? 4 : 8;
+        const int64_t sz_m = (int64_t)t.p_m * (t.p_m + 1) * elem, sz_l = (int64_t)t.p_l * (t.p_l + 1) * elem;
+        const int64_t base_in = j.op == SH_L2L ? t.off_l / sz_l : t.off_m / sz_m;
+        const int64_t base_out = j.op == SH_M2M ? t.off_m / sz_m : t.off_l / sz_l;
+        // one pass: check and pack every translation; destinations unique within the job
+        // (a bit per slot of the destination pool)
+        j.dst.resize(n);
+        j.packed.resize(n * (size_t)(3 * elem + 16));
+        char *pr = j.packed.data();
+        int64_t *ps = reinterpret_cast<int64_t *>(pr + n * 3 * elem), *pd = ps + n;
+        std::vector<uint64_t> mark((size_t)(n_out + 63) / 64, 0);
+        for (size_t i = 0; i < n; ++i) {
+            const double x = job->r[3 * i], y = job->r[3 * i + 1], z = job->r[3 * i + 2];
+            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return SH_ESHIFT;
+            if (j.op == SH_M2L && x == 0 && y == 0 && z == 0) return SH_ESHIFT;
+            const int64_t sv = job->src[i], dv = job->dst[i];
+            if (sv < 0 || sv >= n_in || dv < 0 || dv >= n_out) return SH_EINVAL;
+            uint64_t &w = mark[(size_t)dv >> 6];
+            const uint64_t bit = uint64_t(1) << (dv & 63);
+            if (w & bit) return SH_EINVAL;
+            w |= bit;
+            if (f32) {
+                float *r = reinterpret_cast<float *>(pr) + 3 * i;
+                r[0] = (float)x;
+                r[1] = (float)y;
+                r[2] = (float)z;
+            } else {
+                double *r = reinterpret_cast<double *>(pr) + 3 * i;
+                r[0] = x;
+                r[1] = y;
+                r[2] = z;
+            }
+            ps[i] = base_in + sv;
+            pd[i] = base_out + dv;
+            j.dst[i] = dv;
         }
+        // for M2M / L2L (one pool) no destination is also a source
         if (j.op != SH_M2L)
-            for (int64_t s : j.src)
-                if (mark[(size_t)s]) return SH_EINVAL;
+            for (size_t i = 0; i < n; ++i) {
+                const int64_t sv = job->src[i];
+                if (mark[(size_t)sv >> 6] & (uint64_t(1) << (sv & 63))) return SH_EINVAL;
+            }
         std::lock_guard<std::mutex> lk(S->mu);
         auto it = S->trees.find(j.tree);
-        if (it == S->trees.end()) return SH_EINVAL;
+        // the tree must be the one checked above (destroyed and recreated meanwhile: refuse)
+        if (it == S->trees.end() || it->second.off_m != t.off_m || it->second.off_l != t.off_l ||
+            it->second.dtype != t.dtype || it->second.p_m != t.p_m || it->second.p_l != t.p_l)
+            return SH_EINVAL;
         if (j.footprint > S->cfg.staging_bytes) return SH_EBUSY;  // can never be admitted
         const int64_t id = S->next_job++;
         j.t_submit = now_s();
