@@ -42,6 +42,7 @@ constexpr int kNTW = 5;    // output tiles of 16 per wavefront and work item
 constexpr int kNTC = 4 * kNTW;
 constexpr int kMaxClasses = 4096;
 constexpr int kMaxK = 64 * 65 + 32;  // input reals of order 64, padded
+constexpr int kMaxN = 64 * 65;       // output reals of order 64
 
 // ---------------------------------------------------------------------------------------
 // Operator preparation: T_raw[c][k][n] (FP64, paper basis, row k = image of unit solid k)
@@ -119,8 +120,10 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
     __shared__ s16x8 Ap[NPA][kTM][kKC / 8 + 1];   // BF16 pieces, rows padded by one 16-byte slot
     __shared__ int tiles_before[kMaxClasses + 1];
     __shared__ unsigned char live[kMaxK];
+    __shared__ unsigned char live_o[kMaxN];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int k = tid; k < a.Kp; k += 256) live[k] = a.live_in[k];
+    for (int n = tid; n < a.N; n += 256) live_o[n] = a.live_out[n];
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nclass = a.nclass;
     const int64_t count = a.count;
@@ -201,24 +204,41 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
             // split 64 input rows x kw reals into BF16 pieces in LDS (8 reals per thread step;
             // rows past the class re-read its last row)
             __syncthreads();
-            for (int p = tid; p < kTM * (kw / 8); p += 256) {
+            // every load of the chunk is issued before the first is used (one memory latency
+            // per chunk); addresses are clamped into the solid, and the padding and Im C_n^0
+            // entries are zeroed by the live flags
+            constexpr int IT = kTM * (kKC / 8) / 256;
+            const int lim = kTM * (kw / 8);
+            float x[IT][8];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int p0 = tid + 256 * it;
+                const int p = p0 < lim ? p0 : lim - 1;
+                const int t = p / (kw / 8);
+                const int k = kc + 8 * (p - t * (kw / 8));
+                const int64_t row = first + (t < rows ? t : rows - 1);
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const int kk = k + j < a.K ? k + j : a.K - 2;
+                    const float2 v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + kk);
+                    x[it][j] = v.x;
+                    x[it][j + 1] = v.y;
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int p = tid + 256 * it;
+                if (p >= lim) break;
                 const int t = p / (kw / 8);
                 const int k8 = p - t * (kw / 8);
                 const int k = kc + 8 * k8;
-                const int64_t row = first + (t < rows ? t : rows - 1);
-                float x[8];
 #pragma unroll
-                for (int j = 0; j < 8; j += 2) {
-                    float2 v = make_float2(0.f, 0.f);
-                    if (k + j < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k + j);
-                    x[j] = live[k + j] ? v.x : 0.f;
-                    x[j + 1] = live[k + j + 1] ? v.y : 0.f;
-                }
+                for (int j = 0; j < 8; ++j) x[it][j] = live[k + j] ? x[it][j] : 0.f;
                 s16x8 h, m, l;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const __bf16 hb = (__bf16)x[j];  // v_cvt_pk_bf16_f32: round to nearest even
-                    const float r1 = x[j] - (float)hb;
+                    const __bf16 hb = (__bf16)x[it][j];  // v_cvt_pk_bf16_f32: round to nearest even
+                    const float r1 = x[it][j] - (float)hb;
                     const __bf16 mb = (__bf16)r1;
                     h[j] = __builtin_bit_cast(short, hb);
                     m[j] = __builtin_bit_cast(short, mb);
@@ -290,7 +310,8 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm(SharedArgs a)
             for (int i = 0; i < kNTW; ++i) {
                 const int n = (nt0 + wave + 4 * i) * 16 + (lane & 15);
                 if (n >= a.N) continue;
-                const bool live = a.live_out[n] != 0;
+                const bool live = live_o[n] != 0;  // from LDS: a global load here would wait
+                                                   // for every store issued before it
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int t = mt * 16 + 4 * (lane >> 4) + j;
@@ -314,6 +335,7 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm_f32(SharedArgs a)
     __shared__ float As[kTM][KB][4][8 + 1];  // row padded so that lanes of one row avoid a bank
     __shared__ int tiles_before[kMaxClasses + 1];
     __shared__ unsigned char live[kMaxK];
+    __shared__ unsigned char live_o[kMaxN];
     typedef float f8 __attribute__((ext_vector_type(8)));
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -321,6 +343,7 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm_f32(SharedArgs a)
     const int64_t count = a.count;
     const float *frag = reinterpret_cast<const float *>(a.frag);
     for (int k = tid; k < a.Kp; k += 256) live[k] = a.live_in[k];
+    for (int n = tid; n < a.N; n += 256) live_o[n] = a.live_out[n];
     const int nchunks = (a.NT + kNTC - 1) / kNTC;
     if (wave == 0) {
         int carry = 0;
@@ -378,15 +401,29 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm_f32(SharedArgs a)
         for (int kc = 0; kc < a.Kp; kc += kKC) {
             const int kw = (a.Kp - kc) < kKC ? (a.Kp - kc) : kKC;
             __syncthreads();
-            for (int p = tid; p < kTM * (kw / 2); p += 256) {
+            // every load of the chunk first (one memory latency per chunk), addresses clamped
+            // into the solid, padding and Im C_n^0 zeroed by the live flags
+            constexpr int IT = kTM * (kKC / 2) / 256;
+            const int lim = kTM * (kw / 2);
+            float2 xv[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int p0 = tid + 256 * it;
+                const int p = p0 < lim ? p0 : lim - 1;
                 const int t = p / (kw / 2);
                 const int k = kc + 2 * (p - t * (kw / 2));
                 const int64_t row = first + (t < rows ? t : rows - 1);
-                float2 v = make_float2(0.f, 0.f);
-                if (k < a.K) v = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + k);
+                xv[it] = *reinterpret_cast<const float2 *>(a.in + row * a.ld_in + (k < a.K ? k : a.K - 2));
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int p = tid + 256 * it;
+                if (p >= lim) break;
+                const int t = p / (kw / 2);
+                const int k = kc + 2 * (p - t * (kw / 2));
                 const int r0 = k - kc, r1 = r0 + 1;
-                As[t][r0 >> 5][r0 & 3][(r0 & 31) >> 2] = live[k] ? v.x : 0.f;
-                As[t][r1 >> 5][r1 & 3][(r1 & 31) >> 2] = live[k + 1] ? v.y : 0.f;
+                As[t][r0 >> 5][r0 & 3][(r0 & 31) >> 2] = live[k] ? xv[it].x : 0.f;
+                As[t][r1 >> 5][r1 & 3][(r1 & 31) >> 2] = live[k + 1] ? xv[it].y : 0.f;
             }
             __syncthreads();
             for (int kb = 0; kb < kw / 32; ++kb) {
@@ -422,14 +459,14 @@ __global__ __launch_bounds__(256, 2) void k_shared_gemm_f32(SharedArgs a)
             for (int i = 0; i < kNTW; ++i) {
                 const int n = (nt0 + wave + 4 * i) * 16 + (lane & 15);
                 if (n >= a.N) continue;
-                const bool live_o = a.live_out[n] != 0;
+                const bool live_n = live_o[n] != 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int t = mt * 16 + 4 * (lane >> 4) + j;
                     if (t >= rows) continue;
                     float *o = a.out + (first + t) * a.ld_out + n;
-                    float v = live_o ? acc[mt][i][j] : 0.f;
-                    if (accumulate && live_o) v += *o;
+                    float v = live_n ? acc[mt][i][j] : 0.f;
+                    if (accumulate && live_n) v += *o;
                     *o = v;
                 }
             }

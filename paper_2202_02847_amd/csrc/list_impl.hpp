@@ -31,7 +31,9 @@ __global__ __launch_bounds__(256, (lpt_min_waves<Acc, PB>()))
 void k_list_lpt(DevTables tab, ListArgs la)
 {
     constexpr int SP = lpt_stride<PB>();
-    constexpr bool HOLD = lpt_hold_powers<Acc, PB>();
+    // powers held per lane up to bucket 12 in FP32 (the list kernel keeps its own register
+    // budget; its buckets were tuned with this choice)
+    constexpr bool HOLD = sizeof(Acc) == 4 ? PB <= 12 : lpt_hold_powers<Acc, PB>();
     using P2 = typename Pair<Acc>::T;
     using R2 = typename Pair<Real>::T;
     __shared__ Acc X[64 * SP];

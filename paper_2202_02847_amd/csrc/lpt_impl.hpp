@@ -404,10 +404,23 @@ constexpr int lpt_min_waves_nw()
 {
     return lpt_blocks_per_cu<Acc, PM>() >= 2 || lpt_waves<Acc, PM>() == 8 ? 2 : 1;
 }
+// Powers held in registers (tabulated once per block) up to this order, regenerated per row
+// above.  FP32 from order 9 on regenerates them: with the next block's prefetch also off
+// (lpt_prefetch_ok) the kernel fits in 159 VGPRs at order 10, three wavefronts per SIMD instead
+// of two (FP32 M2L, 2^20 translations at P = 10: 0.258 -> 0.237 ms on one MI355X).
 template <typename Acc, int PM>
 constexpr bool lpt_hold_powers()
 {
-    return sizeof(Acc) == 4 ? PM <= 12 : PM <= 6;
+    return sizeof(Acc) == 4 ? PM <= 8 : PM <= 6;
+}
+// Whether a block's input may be prefetched into registers during the previous block (when it
+// fits in 64 VGPRs): not for FP32 from order 9 on, where the registers buy a third wavefront
+// per SIMD instead (lpt_hold_powers).  Below order 9 the prefetch wins (P = 6: 0.079 ms with it,
+// 0.094 ms without).
+template <typename Real, int PM>
+constexpr bool lpt_prefetch_ok()
+{
+    return !(sizeof(Real) == 4 && PM >= 9);
 }
 
 // Whether the L-side swaps read the M-side table transposed (swap_row_x) instead of the
@@ -472,7 +485,7 @@ void k_lpt(DevTables tab, TransArgs a)
     // backward rotation as well measured no faster than the coalesced store phase, and
     // non-temporal per-lane row stores were 2.5x slower: partial-line writes.)
     constexpr bool DIRECT = NW == 8;
-    constexpr bool PREFETCH = !DIRECT && LIT * 2 * (int)sizeof(Real) / 4 <= 64;
+    constexpr bool PREFETCH = !DIRECT && LIT * 2 * (int)sizeof(Real) / 4 <= 64 && lpt_prefetch_ok<Real, PM>();
     constexpr int CH = PREFETCH ? LIT : 16 * 4 / (int)sizeof(Real);  // loads per batch
     R2 pre[CH];
     Real prx = 0, pry = 0, prz = 1;
