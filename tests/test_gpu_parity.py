@@ -402,3 +402,21 @@ def test_concurrent_host_threads(ctx, orc):
     assert not errs
     for o in outs:
         assert torch.equal(o, serial)
+
+
+def test_indexed_call_needs_both_index_arrays(ctx):
+    """An indexed call with only one of its index arrays is rejected before any launch (the
+    indexed kernels read both): SH_EINVAL, nothing written."""
+    torch, dev = torch_dev()
+    S = size(10)
+    x = torch.full((4, S), 3.0, dtype=torch.float64, device=dev)
+    y = torch.full((4, S), 5.0, dtype=torch.float64, device=dev)
+    r = torch.ones((4, 3), dtype=torch.float64, device=dev)
+    idx = torch.arange(4, dtype=torch.int64, device=dev)
+    L = sh.lib()
+    for src, dst in ((idx.data_ptr(), None), (None, idx.data_ptr())):
+        st = L.sh_translate_indexed(ctx.handle, sh.SH_M2L, sh.SH_F64, 10, 10, 4, r.data_ptr(), src, x.data_ptr(), S,
+                                    dst, y.data_ptr(), S, 0, None)
+        assert st == sh.SH_EINVAL
+    torch.cuda.synchronize()
+    assert bool((y == 5.0).all())
