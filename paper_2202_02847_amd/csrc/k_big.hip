@@ -145,12 +145,14 @@ __device__ __forceinline__ void load_row_frag(const double *__restrict__ frag, i
             for (int ks = 0; ks < 4; ++ks) f.a[pm][q][ks] = F[((pm * 2 + q) * 4 + ks) * 64];
 }
 
-// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks.  Each lane
-// reads (re, im) of the two input orders of its K index and step (one per parity) before the
-// first product; orders past the degree read a valid address and are replaced by zero.  With
-// RAW the row holds the input as loaded: Im C_n^0 is dropped, and the scale and the rotation by
-// e^{i m alpha} are applied here.
-template <bool RAW>
+// Swap of row n of the 16 solids: D[pm][q] = (output parity pm, part q) blocks; NP = n & 1 (so
+// that the input parity each block takes is known at compile time).  Each lane reads (re, im)
+// of the two input orders of its K index and step (one per parity) before the first product.
+// Orders past the degree read order n instead: the operator fragments are zero there (and zero
+// in the imaginary part at order 0), so those products add exact zeros.  With RAW the row holds
+// the input as loaded: Im C_n^0 is dropped, and the scale and the rotation by e^{i m alpha} are
+// applied here.
+template <bool RAW, int NP>
 __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, const BigLds &L, int n, int lane,
                                          d4 (&D)[2][2])
 {
@@ -158,28 +160,24 @@ __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, cons
     const int t = lane & 15, kg = lane >> 4;
     const double *Xn = X + xe(n * (n + 1) / 2, t);
     const double sc = RAW ? L.scin[n * kBT + t] : 1.0;
-    double b[2][2][4];
+    double b[2][2][4];  // [input parity][part][K step]
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
         if (ks >= ks_n) break;
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             const int lc = 2 * (4 * ks + kg) + par;
-            const bool ok = lc <= n;
-            const int l = ok ? lc : 0;
+            const int l = lc <= n ? lc : n;
             const double2 v = lds2(Xn + l * 2 * kBT);
             double re = v.x, im = v.y;
             if (RAW) {
                 const double2 cs = lds2(L.pw + pwi(0, l, t));
                 const double a = re * sc, c = l ? im * sc : 0.0;
                 re = a * cs.x - c * cs.y;
-                im = l ? a * cs.y + c * cs.x : 0.0;
+                im = a * cs.y + c * cs.x;
             }
-            // input parity par feeds (pm, q) with (n + pm + q) & 1 == par
-            const int pm0 = (par + n) & 1, pm1 = (par + n + 1) & 1;
-            const double r0 = ok ? re : 0.0, i0 = ok ? im : 0.0;
-            if (pm0) b[1][0][ks] = r0; else b[0][0][ks] = r0;
-            if (pm1) b[1][1][ks] = i0; else b[0][1][ks] = i0;
+            b[par][0][ks] = re;
+            b[par][1][ks] = im;
         }
     }
 #pragma unroll
@@ -192,13 +190,14 @@ __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, cons
 #pragma unroll
         for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) D[pm][q] = mfma64(f.a[pm][q][ks], b[pm][q][ks], D[pm][q]);
+            for (int q = 0; q < 2; ++q) D[pm][q] = mfma64(f.a[pm][q][ks], b[(NP + pm + q) & 1][q][ks], D[pm][q]);
     }
 }
 
 // Second swap of a row straight from the first swap's output registers: in the D layout,
 // element j of lane group g holds order m = 2 (4 j + g) + p of parity block p, which is exactly
 // the B operand of K step j, K index g, for the input-parity p = (n + pm + q) & 1 blocks.
+template <int NP>
 __device__ __forceinline__ void swap_row_regs(const RowFrag &f, int n, const d4 (&Din)[2][2], d4 (&D)[2][2])
 {
     const int ks_n = big_ks(n);
@@ -212,10 +211,7 @@ __device__ __forceinline__ void swap_row_regs(const RowFrag &f, int n, const d4 
 #pragma unroll
         for (int pm = 0; pm < 2; ++pm)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int pl = (n + pm + q) & 1;
-                D[pm][q] = mfma64(f.a[pm][q][ks], pl ? Din[1][q][ks] : Din[0][q][ks], D[pm][q]);
-            }
+            for (int q = 0; q < 2; ++q) D[pm][q] = mfma64(f.a[pm][q][ks], Din[(NP + pm + q) & 1][q][ks], D[pm][q]);
     }
 }
 
@@ -402,9 +398,15 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     {
         auto row = [&](const RowFrag &f, int n) {
             d4 D[2][2], E[2][2];
-            swap_row<direct>(f, X, L, n, lane, D);
-            rotate_beta(L, n, lane, D, 1.0);
-            swap_row_regs(f, n, D, E);
+            if (n & 1) {
+                swap_row<direct, 1>(f, X, L, n, lane, D);
+                rotate_beta(L, n, lane, D, 1.0);
+                swap_row_regs<1>(f, n, D, E);
+            } else {
+                swap_row<direct, 0>(f, X, L, n, lane, D);
+                rotate_beta(L, n, lane, D, 1.0);
+                swap_row_regs<0>(f, n, D, E);
+            }
             write_row(X, L, n, lane, E, false);
         };
         auto fetch = [&](int n, RowFrag &f) {
@@ -496,9 +498,15 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     {
         auto row = [&](const RowFrag &f, int n) {
             d4 D[2][2], E[2][2];
-            swap_row<false>(f, X, L, n, lane, D);
-            rotate_beta(L, n, lane, D, -1.0);
-            swap_row_regs(f, n, D, E);
+            if (n & 1) {
+                swap_row<false, 1>(f, X, L, n, lane, D);
+                rotate_beta(L, n, lane, D, -1.0);
+                swap_row_regs<1>(f, n, D, E);
+            } else {
+                swap_row<false, 0>(f, X, L, n, lane, D);
+                rotate_beta(L, n, lane, D, -1.0);
+                swap_row_regs<0>(f, n, D, E);
+            }
             if (fused)
                 store_row<Real>(aout, L, n, lane, E, nt);  // rotate by -alpha, unscale, store
             else
