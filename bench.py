@@ -143,7 +143,9 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     """Shared-direction M2L at order P: 2^20 translations grouped by the 316 octree offsets,
     FP32 normalised solids.  Times the BF16x6 and BF16x3 matrix-core paths, the FP32 and
     FP64 rotation paths on the same multipoles, and states each FP32 path's per-degree error
-    against the FP64 GPU path (itself held to 1e-12 of the oracle by the tests)."""
+    against the FP64 GPU path (itself held to 1e-12 of the oracle by the tests): *_err against
+    the FP64 result of the FP64 input, *_arith_err against the FP64 result of the FP32-rounded
+    input (the form's own arithmetic), and input_rounding_err between those two references."""
     from paper_2202_02847_amd import workloads as wl
 
     c = wl.config2(n_m2l=n, n_child=8, npts=32, P=P, seed_config=3)
@@ -171,11 +173,22 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
     rng = np.random.default_rng(0)
     pick = torch.from_numpy(np.sort(rng.choice(n, sample, replace=False))).to(dev)
     ref = (d_L64[pick] * wL).cpu().numpy()  # FP64 result in the normalised basis
+    # the FP64 path on the FP32-rounded input (and shift): the exact result an FP32 entry point
+    # can reach; its distance from ref is what rounding the input alone costs
+    d_Mr = d_M32.double() / wM
     d_r32 = d_r64.float()
+    d_Lr = torch.empty_like(d_L64)
+    sh.sh_m2l_batch_f64(ctx, P, P, n, d_r32.double(), d_Mr, S, d_Lr, S)
+    ref_r = (d_Lr[pick] * wL).cpu().numpy()
+    del d_Mr, d_Lr
+    e = degree_error(ref_r, ref, P)
+    res["input_rounding_err_max"], res["input_rounding_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
     t = time_launch(torch, lambda: sh.sh_m2l_batch_f32(ctx, P, P, n, d_r32, d_M32, S, d_L32, S), reps)
     res["rot_f32_per_s"] = n / t
-    e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
+    got = d_L32[pick].double().cpu().numpy()
+    e, ea = degree_error(got, ref, P), degree_error(got, ref_r, P)
     res["rot_f32_err_max"], res["rot_f32_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
+    res["rot_f32_arith_err_max"], res["rot_f32_arith_err_p99"] = float(ea.max()), float(np.quantile(ea, 0.99))
     bpt = bytes_per_translation(P, P, 4) - 12  # FP32 solids in and out, no shift array
     for prec, name in ((sh.SH_SHARED_BF16X6, "bf16x6"), (sh.SH_SHARED_BF16X3, "bf16x3"), (sh.SH_SHARED_FP32, "fp32mfma")):
         t0 = time.perf_counter()
@@ -192,8 +205,10 @@ def run_precision(sh, ctx, torch, dev, P=16, n=1 << 20, reps=5, sample=4096):
             products = 6 if prec == sh.SH_SHARED_BF16X6 else 3
             res[f"{name}_frac_mfma_bf16"] = 2.0 * S * S * products * n / t / 2.5e15
         res[f"{name}_frac_hbm"] = bpt * n / t / 1e9 / HBM_PEAK_GBS
-        e = degree_error(d_L32[pick].double().cpu().numpy(), ref, P)
+        got = d_L32[pick].double().cpu().numpy()
+        e, ea = degree_error(got, ref, P), degree_error(got, ref_r, P)
         res[f"{name}_err_max"], res[f"{name}_err_p99"] = float(e.max()), float(np.quantile(e, 0.99))
+        res[f"{name}_arith_err_max"], res[f"{name}_arith_err_p99"] = float(ea.max()), float(np.quantile(ea, 0.99))
         op.close()
     del d_M, d_M32, d_L64, d_L32
     torch.cuda.empty_cache()

@@ -275,3 +275,39 @@ def test_server_shared_tree_order_and_alone_equals_mix(ctx, orc):
     op, r, s, d = jobs[7]
     exp[d] = orc.translate_batch("l2l", P, P, r, exp[s])
     check(mixed, exp, P, "L", 4 * TOL[sh.SH_F64], "shared tree")
+
+
+@pytest.mark.parametrize("dtype", [sh.SH_F64, sh.SH_F32], ids=DT_ID.get)
+def test_server_trees_of_one_order_share_a_call(ctx, orc, dtype):
+    """Jobs on several trees of the same dtype and orders are fused into one indexed call per
+    operation (slots addressed from the start of the pool arena): each job's result equals the
+    oracle's and, bit for bit, the same job run alone on its own server."""
+    P, n = 7, 400
+    ops = ["m2l", "m2m", "m2l", "l2l", "m2l"]
+    print(f"[server] shared call {DT_ID[dtype]}", flush=True)
+
+    def run(which):
+        srv = sh.Server(ctx, pool_bytes=64 << 20, staging_bytes=8 << 20, streams=1, max_batch_jobs=16)
+        # a tree of another order first, so the pools of interest do not start at offset 0
+        srv.tree_create(dtype, 5, 37, 9, 11)
+        trees = [make_tree(srv, orc, dtype, P, n, 40 + k) for k in range(len(ops))]
+        ids = [srv.submit(trees[k][0], ops[k], *job_arrays(ops[k], n, 150 + 7 * k, 60 + k)) for k in which]
+        for i in ids:
+            srv.wait(i)
+        st = srv.stats()
+        outs = {k: read_pool(srv, trees[k][0], 0 if ops[k] == "m2m" else 1, P, n, dtype)[1] for k in which}
+        srv.close()
+        return outs, trees, st
+
+    together, trees, st = run(range(len(ops)))
+    print(f"[server] shared call: {st['batches']} batches for {len(ops)} jobs", flush=True)
+    for k, op in enumerate(ops):
+        alone, _, _ = run([k])
+        assert np.array_equal(alone[k], together[k]), f"job {k} ({op}) differs alone and fused"
+        t, M, L = trees[k]
+        r, src, dst = job_arrays(op, n, 150 + 7 * k, 60 + k)
+        C = M if op != "l2l" else L
+        kind_in = "M" if op != "l2l" else "L"
+        Cin = from_basis(to_basis(C, P, kind_in, dtype), P, kind_in, dtype)
+        out = from_basis(together[k], P, "M" if op == "m2m" else "L", dtype)
+        check_job(orc, dtype, op, P, r, Cin[src] if dtype == sh.SH_F64 else C[src], out[dst], f"shared call {op}")
