@@ -267,7 +267,7 @@ def _serving_stats(st, rate, staging):
 
 
 def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, staging=10 << 20,
-                sat_jobs=600):
+                sat_jobs=600, sat_threads=4):
     """The serving workload: a Poisson stream (mean `rate` jobs/s, for `seconds`) of jobs of
     10^3..10^5 translations (log-uniform), one order P in {4, 8, 16, 24, 30} and one dtype
     (FP32 or FP64) per job, on resident trees (one per order and dtype, n_slots multipoles and
@@ -276,7 +276,8 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
     so admission defers jobs under bursts.  Latency: submission to completion.
 
     Then a saturation leg: `sat_jobs` jobs of the same distribution queued at once (closed
-    loop), through a new server with a staging budget 8x larger, against the same job stream
+    loop) by `sat_threads` client threads, through a new server with a staging budget 8x
+    larger, against the same job stream
     issued as plain calls: per job, its shift and slot arrays copied from the same host arrays
     to the device and one indexed batched call, on one stream.  Both legs are timed from the
     first submission (call) to the last completion; submit_s is the served leg's submission
@@ -316,9 +317,25 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
     sat_staging = 8 * staging
     srv = sh.Server(ctx, pool_bytes=pool + (64 << 20), staging_bytes=sat_staging, streams=4, max_batch_jobs=64)
     trees = _serving_trees(sh, srv, n_slots)
+    # clients: sat_threads host threads submit the jobs round robin (each call checks and packs
+    # its job on the calling thread, outside the server lock)
+    import threading
+
+    ids_by = [[] for _ in range(sat_threads)]
+
+    def client(k):
+        for i in range(k, len(jobs), sat_threads):
+            P, dt, op, r, src, dst = jobs[i]
+            ids_by[k].append(srv.submit(trees[(P, dt)], op, r, src, dst))
+
     t0 = time.perf_counter()
-    ids = [srv.submit(trees[(P, dt)], op, r, src, dst) for P, dt, op, r, src, dst in jobs]
+    ths = [threading.Thread(target=client, args=(k,)) for k in range(sat_threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
     t_submit = time.perf_counter() - t0
+    ids = [i for b in ids_by for i in b]
     srv.drain()
     for i in ids:
         srv.wait(i)
@@ -367,6 +384,7 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
     sat["plain_device_resident_s"] = round(t_resident, 4)
     sat["served_over_plain_device_resident"] = round(t_resident / max(sat["duration_s"], 1e-9), 3)
     sat["submit_s"] = round(t_submit, 4)
+    sat["submit_threads"] = sat_threads
     sat["plain_translations_per_s"] = ntr / t_plain
     sat["plain_s"] = round(t_plain, 4)
     sat["served_over_plain"] = round(sat["translations_per_s"] / sat["plain_translations_per_s"], 3)
