@@ -29,9 +29,10 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kBT = 16;     // translations per block
-constexpr int kWaves = 8;   // wavefronts per workgroup (two per SIMD, to hide each other's latency)
-constexpr int kThreads = 64 * kWaves;
-static_assert(kThreads == kBT * kBigOrder, "the power tables take one thread per (order, translation)");
+// Wavefronts per workgroup: 8 (two per SIMD, hiding each other's latency) where a block's LDS
+// leaves room for one workgroup per CU; 4 where two workgroups fit (orders up to 21), so that two
+// blocks are in flight per CU and one's z-step overlaps the other's memory streams.
+constexpr int kLdsPerCu = 160 * 1024;
 
 template <typename Real>
 struct Pair2;
@@ -50,6 +51,7 @@ struct Pair2<float> {
 constexpr int kBigPairs = kBigOrder * (kBigOrder + 1) / 2;
 static_assert(kBigPairs % 4 == 0, "the pair table fills whole doubles");
 struct BigLds {
+    int pm;  // order stride of the power and scale tables (the block's largest order)
     double *X, *pw, *scin, *scout, *r;
     int64_t *ioff, *ooff;
     int *bad;
@@ -65,9 +67,9 @@ __host__ __device__ constexpr BigLdsOffsets big_lds_offsets(int PM)
     BigLdsOffsets o{};
     o.X = kBigPairs / 4;
     o.pw = o.X + (size_t)PM * (PM + 1) * kBT;
-    o.scin = o.pw + 4 * kBigOrder * kBT;
-    o.scout = o.scin + kBigOrder * kBT;
-    o.ioff = o.scout + kBigOrder * kBT;
+    o.scin = o.pw + 4 * (size_t)PM * kBT;
+    o.scout = o.scin + (size_t)PM * kBT;
+    o.ioff = o.scout + (size_t)PM * kBT;
     o.ooff = o.ioff + kBT;
     o.r = o.ooff + kBT;
     o.bad = o.r + 3 * kBT;
@@ -80,6 +82,7 @@ __device__ __forceinline__ BigLds big_lds(double *sm, int PM)
 {
     const BigLdsOffsets o = big_lds_offsets(PM);
     BigLds L;
+    L.pm = PM;
     L.nm = reinterpret_cast<unsigned short *>(sm);
     L.X = sm + o.X;
     L.pw = sm + o.pw;
@@ -120,7 +123,7 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
 // imaginary part, so one 16-byte LDS access moves both.
 __device__ __forceinline__ int xe(int p, int t) { return (p * kBT + t) * 2; }
 // Index of (cos, sin) of m times angle k (0: alpha, 1: beta) of translation t in the power table.
-__device__ __forceinline__ int pwi(int k, int m, int t) { return ((k * kBigOrder + m) * kBT + t) * 2; }
+__device__ __forceinline__ int pwi(const BigLds &L, int k, int m, int t) { return ((k * L.pm + m) * kBT + t) * 2; }
 __device__ __forceinline__ double2 lds2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
 __device__ __forceinline__ void sts2(double *p, double a, double b) { *reinterpret_cast<double2 *>(p) = double2{a, b}; }
 // Waits until every vector memory operation this wavefront has issued is complete (the
@@ -171,7 +174,7 @@ __device__ __forceinline__ void swap_row(const RowFrag &f, const double *X, cons
             const double2 v = lds2(Xn + l * 2 * kBT);
             double re = v.x, im = v.y;
             if (RAW) {
-                const double2 cs = lds2(L.pw + pwi(0, l, t));
+                const double2 cs = lds2(L.pw + pwi(L, 0, l, t));
                 const double a = re * sc, c = l ? im * sc : 0.0;
                 re = a * cs.x - c * cs.y;
                 im = a * cs.y + c * cs.x;
@@ -225,7 +228,7 @@ __device__ __forceinline__ void rotate_beta(const BigLds &L, int n, int lane, d4
         for (int j = 0; j < 4; ++j) {
             const int m = 2 * (4 * j + g) + pm;
             if (m > n) continue;
-            const double2 cs = lds2(L.pw + pwi(1, m, t));
+            const double2 cs = lds2(L.pw + pwi(L, 1, m, t));
             const double s = sgn * cs.y;
             const double re = D[pm][0][j], im = D[pm][1][j];
             D[pm][0][j] = re * cs.x - im * s;
@@ -248,7 +251,7 @@ __device__ __forceinline__ void write_row(double *X, const BigLds &L, int n, int
             if (m > n) continue;
             double re = D[pm][0][j], im = D[pm][1][j];
             if (unrotate) {
-                const double2 cs = lds2(L.pw + pwi(0, m, t));
+                const double2 cs = lds2(L.pw + pwi(L, 0, m, t));
                 const double a = re;
                 re = (a * cs.x + im * cs.y) * f;
                 im = (im * cs.x - a * cs.y) * f;
@@ -274,7 +277,7 @@ __device__ __forceinline__ void store_row(Real *__restrict__ aout, const BigLds 
         for (int j = 0; j < 4; ++j) {
             const int m = 2 * (4 * j + g) + pm;
             if (m > n) continue;
-            const double2 cs = lds2(L.pw + pwi(0, m, t));
+            const double2 cs = lds2(L.pw + pwi(L, 0, m, t));
             const double re = D[pm][0][j], im = D[pm][1][j];
             R2 w;
             w.x = (Real)((re * cs.x + im * cs.y) * f);
@@ -301,7 +304,7 @@ __device__ __forceinline__ void dma_row(const double *__restrict__ ain, const Bi
 
 // One block of up to 16 translations whose offsets and shifts are in L (t >= nt repeat the
 // last valid translation and are not stored).
-template <typename Real, int OP>
+template <typename Real, int OP, int NW>
 __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p_out, int nt, const Real *__restrict__ ain,
                           Real *__restrict__ aout, bool acc_out, int *err)
 {
@@ -312,6 +315,7 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     constexpr bool direct = sizeof(Real) == 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int kWaves = NW, kThreads = 64 * NW;
     double *X = L.X;
     auto row_of = [&](int n0) { return n0 + (((n0 / kWaves) & 1) ? kWaves - 1 - wave : wave); };
 
@@ -320,9 +324,9 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     }
 
     // ---- geometry, powers and scales: thread (m, t) fills order m of translation t, every
-    // order below kBigOrder (powers by repeated squaring) ----
-    {
-        const int t = tid & 15, m = tid >> 4;
+    // order below the block's largest (powers by repeated squaring) ----
+    for (int mt = tid; mt < L.pm * kBT; mt += kThreads) {
+        const int t = mt & 15, m = mt >> 4;
         const Geometry g = shift_geometry(L.r[3 * t], L.r[3 * t + 1], L.r[3 * t + 2]);
         const bool ok = g.valid == 1;
         if (m == 0) L.bad[t] = ok ? 0 : (g.valid == 0 ? 1 : 2);
@@ -350,8 +354,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
             R *= R;
             sr *= sr;
         }
-        sts2(L.pw + pwi(0, m, t), c1, s1m);
-        sts2(L.pw + pwi(1, m, t), c2, s2m);
+        sts2(L.pw + pwi(L, 0, m, t), c1, s1m);
+        sts2(L.pw + pwi(L, 1, m, t), c2, s2m);
         // rn = R^m, sn = s^m
         L.scin[m * kBT + t] = (OP == OP_L2L) ? rn : sn * s1;
         L.scout[m * kBT + t] = (OP == OP_M2M) ? rn * R1 : sn;
@@ -365,25 +369,25 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
     // of translation t, so its source row and the immediate offsets of its loads and LDS stores
     // are fixed; each thread has all of its loads in flight before it uses one ----
     if constexpr (!direct) {
-        constexpr int U = 16;
+        constexpr int U = 16, TS = kThreads / 16;  // threads per translation
         const int t = tid & 15, s0 = tid >> 4;
         const int npin = p_in * (p_in + 1) / 2;
         const R2 *src = reinterpret_cast<const R2 *>(ain + L.ioff[t]);
-        for (int base = 0; base < npin; base += 32 * U) {
+        for (int base = 0; base < npin; base += TS * U) {
             R2 v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int p = base + s0 + 32 * u;
+                const int p = base + s0 + TS * u;
                 v[u] = p < npin ? src[p] : R2{};
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int p = base + s0 + 32 * u;
+                const int p = base + s0 + TS * u;
                 if (p >= npin) break;
                 const int nm = L.nm[p], n = nm >> 5, m = nm & 31;
                 const double f = L.scin[n * kBT + t];
                 const double a = (double)v[u].x * f, b = m ? (double)v[u].y * f : 0.0;
-                const double2 cs = lds2(L.pw + pwi(0, m, t));
+                const double2 cs = lds2(L.pw + pwi(L, 0, m, t));
                 sts2(X + xe(p, t), a * cs.x - b * cs.y, m ? a * cs.y + b * cs.x : 0.0);
             }
         }
@@ -562,8 +566,8 @@ __device__ void big_block(const DevTables &tab, const BigLds &L, int p_in, int p
 }
 
 // Batched form: translation i = 16 b + t of the call.
-template <typename Real, int OP, bool IDX>
-__global__ __launch_bounds__(kThreads) void k_big(DevTables tab, TransArgs a)
+template <typename Real, int OP, bool IDX, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_big(DevTables tab, TransArgs a)
 {
     extern __shared__ double sm[];
     const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
@@ -587,24 +591,35 @@ __global__ __launch_bounds__(kThreads) void k_big(DevTables tab, TransArgs a)
             L.r[3 * t + 2] = (double)rr[3 * i + 2];
         }
         __syncthreads();
-        big_block<Real, OP>(tab, L, a.p_in, a.p_out, nt, ain, aout, (a.flags & 1u) != 0, a.err);
+        big_block<Real, OP, NW>(tab, L, a.p_in, a.p_out, nt, ain, aout, (a.flags & 1u) != 0, a.err);
     }
 }
 
-template <typename Real, int OP, bool IDX>
-hipError_t launch_big_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
+template <typename Real, int OP, bool IDX, int NW>
+hipError_t launch_big_nw(const DevTables &tab, const TransArgs &a, hipStream_t s)
 {
+    constexpr int kThreads = 64 * NW;
     const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
     const size_t smem = big_lds_doubles(PM) * sizeof(double);
-    const void *fn = reinterpret_cast<const void *>(&k_big<Real, OP, IDX>);
+    const void *fn = reinterpret_cast<const void *>(&k_big<Real, OP, IDX, NW>);
     int dev = 0, cu = 256, occ = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, smem) != hipSuccess || occ < 1) occ = 1;
     const int64_t nblk = (a.count + kBT - 1) / kBT;
     const int64_t res = (int64_t)cu * occ;
     const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(kThreads);
-    hipLaunchKernelGGL((k_big<Real, OP, IDX>), grid, block, smem, s, tab, a);
+    hipLaunchKernelGGL((k_big<Real, OP, IDX, NW>), grid, block, smem, s, tab, a);
     return hipGetLastError();
+}
+
+// Two workgroups of 4 wavefronts per CU where two blocks' LDS fit, else one of 8.
+__host__ __device__ constexpr bool big_two_per_cu(int PM) { return 2 * big_lds_doubles(PM) * sizeof(double) <= kLdsPerCu; }
+
+template <typename Real, int OP, bool IDX>
+hipError_t launch_big_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
+{
+    const int PM = a.p_in > a.p_out ? a.p_in : a.p_out;
+    return big_two_per_cu(PM) ? launch_big_nw<Real, OP, IDX, 4>(tab, a, s) : launch_big_nw<Real, OP, IDX, 8>(tab, a, s);
 }
 
 template <typename Real, bool IDX>
@@ -617,8 +632,8 @@ hipError_t launch_big_op(const DevTables &tab, const TransArgs &a, hipStream_t s
 
 // Work-list form: one task (up to 16 items of one operation sharing (p_in, p_out)) per
 // workgroup pass; the LDS is sized for the bin's largest order.
-template <typename Real, int OP>
-__global__ __launch_bounds__(kThreads) void k_big_list(DevTables tab, ListArgs la)
+template <typename Real, int OP, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_big_list(DevTables tab, ListArgs la)
 {
     extern __shared__ double sm[];
     const Real *ain = reinterpret_cast<const Real *>(la.arena_in);
@@ -638,22 +653,30 @@ __global__ __launch_bounds__(kThreads) void k_big_list(DevTables tab, ListArgs l
             L.r[3 * t + 2] = it.r[2];
         }
         __syncthreads();
-        big_block<Real, OP>(tab, L, p_in, p_out, nt, ain, aout, (la.flags & 1u) != 0, la.err);
+        big_block<Real, OP, NW>(tab, L, p_in, p_out, nt, ain, aout, (la.flags & 1u) != 0, la.err);
     }
 }
 
-template <typename Real, int OP>
-hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pmax, hipStream_t s)
+template <typename Real, int OP, int NW>
+hipError_t launch_big_list_nw(const DevTables &tab, const ListArgs &la, int pmax, hipStream_t s)
 {
+    constexpr int kThreads = 64 * NW;
     const size_t smem = big_lds_doubles(pmax) * sizeof(double);
-    const void *fn = reinterpret_cast<const void *>(&k_big_list<Real, OP>);
+    const void *fn = reinterpret_cast<const void *>(&k_big_list<Real, OP, NW>);
     int dev = 0, cu = 256, occ = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, smem) != hipSuccess || occ < 1) occ = 1;
     const int64_t res = (int64_t)cu * occ;
     const dim3 grid((unsigned)(la.ntasks < res ? la.ntasks : res)), block(kThreads);
-    hipLaunchKernelGGL((k_big_list<Real, OP>), grid, block, smem, s, tab, la);
+    hipLaunchKernelGGL((k_big_list<Real, OP, NW>), grid, block, smem, s, tab, la);
     return hipGetLastError();
+}
+
+template <typename Real, int OP>
+hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pmax, hipStream_t s)
+{
+    return big_two_per_cu(pmax) ? launch_big_list_nw<Real, OP, 4>(tab, la, pmax, s)
+                                : launch_big_list_nw<Real, OP, 8>(tab, la, pmax, s);
 }
 
 template <typename Real>
