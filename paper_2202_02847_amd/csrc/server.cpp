@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -513,6 +515,8 @@ sh_status sh_server_tree_create(sh_server *S, int dtype, int p_m, int64_t n_m, i
         // address every tree's slots by solid index from the arena's start; the allocation
         // holds one solid of slack for that
         const int64_t sz_m = (int64_t)p_m * (p_m + 1) * elem, sz_l = (int64_t)p_l * (p_l + 1) * elem;
+        // the pools' byte sizes must not overflow (checked by division)
+        if (n_m > INT64_MAX / sz_m - 2 || n_l > INT64_MAX / sz_l - 2) return SH_EBUSY;
         t.bytes_m = std::max<int64_t>(kAlign, (n_m + 1) * sz_m);
         t.bytes_l = std::max<int64_t>(kAlign, (n_l + 1) * sz_l);
         std::lock_guard<std::mutex> lk(S->mu);

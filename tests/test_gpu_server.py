@@ -198,6 +198,10 @@ def test_server_validation(ctx):
             return e.status
 
     assert status() == sh.SH_OK
+    # pools whose byte size would overflow have no room (checked before any arithmetic wraps)
+    with pytest.raises(sh.ShError) as e:
+        srv.tree_create(sh.SH_F64, 30, 1 << 62, 30, 10)
+    assert e.value.status == sh.SH_EBUSY
     assert status(dst=[4, 5, 5, 7]) == sh.SH_EINVAL          # repeated destination
     assert status(op="m2m", dst=[1, 5, 6, 7]) == sh.SH_EINVAL  # destination is a source
     assert status(dst=[4, 5, 6, 100]) == sh.SH_EINVAL        # slot out of range
