@@ -277,7 +277,8 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
 
     Then a saturation leg: `sat_jobs` jobs of the same distribution queued at once (closed
     loop) by `sat_threads` client threads, through a new server with a staging budget 8x
-    larger, against the same job stream
+    larger (one untimed pass, then the statistics window is reset and a second pass timed;
+    each plain leg below is likewise run once untimed first), against the same job stream
     issued as plain calls: per job, its shift and slot arrays copied from the same host arrays
     to the device and one indexed batched call, on one stream.  Both legs are timed from the
     first submission (call) to the last completion; submit_s is the served leg's submission
@@ -321,24 +322,32 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
     # its job on the calling thread, outside the server lock)
     import threading
 
-    ids_by = [[] for _ in range(sat_threads)]
+    def served_pass():
+        ids_by = [[] for _ in range(sat_threads)]
 
-    def client(k):
-        for i in range(k, len(jobs), sat_threads):
-            P, dt, op, r, src, dst = jobs[i]
-            ids_by[k].append(srv.submit(trees[(P, dt)], op, r, src, dst))
+        def client(k):
+            for i in range(k, len(jobs), sat_threads):
+                P, dt, op, r, src, dst = jobs[i]
+                ids_by[k].append(srv.submit(trees[(P, dt)], op, r, src, dst))
 
-    t0 = time.perf_counter()
-    ths = [threading.Thread(target=client, args=(k,)) for k in range(sat_threads)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
-    t_submit = time.perf_counter() - t0
-    ids = [i for b in ids_by for i in b]
-    srv.drain()
-    for i in ids:
-        srv.wait(i)
+        t0 = time.perf_counter()
+        ths = [threading.Thread(target=client, args=(k,)) for k in range(sat_threads)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        t_submit = time.perf_counter() - t0
+        srv.drain()
+        for b in ids_by:
+            for i in b:
+                srv.wait(i)
+        return t_submit
+
+    # one untimed pass first, as the plain legs below run on warm allocators: the server's
+    # pack buffers and staging are then in use, as in a server under steady load
+    served_pass()
+    srv.stats_reset()
+    t_submit = served_pass()
     sat = _serving_stats(srv.stats(), None, sat_staging)
     srv.close()
     torch.cuda.empty_cache()
@@ -348,20 +357,25 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
         for dt in (sh.SH_F64, sh.SH_F32):
             tdt = torch.float64 if dt == sh.SH_F64 else torch.float32
             pools[(P, dt)] = [torch.full((n_slots, P * (P + 1)), 1e-2, dtype=tdt, device=dev) for _ in range(2)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for P, dt, op, r, src, dst in jobs:
-        # the job as the server receives it: host arrays, shifts converted to the pool's dtype
-        npdt = np.float64 if dt == sh.SH_F64 else np.float32
-        d_r = torch.from_numpy(np.ascontiguousarray(r, npdt)).to(dev, non_blocking=True)
-        d_s = torch.from_numpy(np.ascontiguousarray(src, np.int64)).to(dev, non_blocking=True)
-        d_d = torch.from_numpy(np.ascontiguousarray(dst, np.int64)).to(dev, non_blocking=True)
-        Mp, Lp = pools[(P, dt)]
-        S = P * (P + 1)
-        inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
-        sh.sh_translate_indexed(ctx, op, dt, P, P, len(src), d_r, d_s, inp, S, d_d, out, S)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+
+    def plain_pass():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for P, dt, op, r, src, dst in jobs:
+            # the job as the server receives it: host arrays, shifts converted to the pool's dtype
+            npdt = np.float64 if dt == sh.SH_F64 else np.float32
+            d_r = torch.from_numpy(np.ascontiguousarray(r, npdt)).to(dev, non_blocking=True)
+            d_s = torch.from_numpy(np.ascontiguousarray(src, np.int64)).to(dev, non_blocking=True)
+            d_d = torch.from_numpy(np.ascontiguousarray(dst, np.int64)).to(dev, non_blocking=True)
+            Mp, Lp = pools[(P, dt)]
+            S = P * (P + 1)
+            inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
+            sh.sh_translate_indexed(ctx, op, dt, P, P, len(src), d_r, d_s, inp, S, d_d, out, S)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    plain_pass()  # warm: torch's caching allocator holds the job arrays' sizes
+    t_plain = plain_pass()
     # the same calls with every job's arrays already on the device (their transfer not timed):
     # the device-side lower bound of the plain path
     dev_jobs = []
@@ -370,15 +384,20 @@ def run_serving(sh, ctx, torch, dev, seconds=50.0, rate=200.0, n_slots=1 << 18, 
         dev_jobs.append((P, dt, op, len(src), torch.from_numpy(np.ascontiguousarray(r, npdt)).to(dev),
                          torch.from_numpy(np.ascontiguousarray(src, np.int64)).to(dev),
                          torch.from_numpy(np.ascontiguousarray(dst, np.int64)).to(dev)))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for P, dt, op, count, d_r, d_s, d_d in dev_jobs:
-        Mp, Lp = pools[(P, dt)]
-        S = P * (P + 1)
-        inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
-        sh.sh_translate_indexed(ctx, op, dt, P, P, count, d_r, d_s, inp, S, d_d, out, S)
-    torch.cuda.synchronize()
-    t_resident = time.perf_counter() - t0
+
+    def resident_pass():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for P, dt, op, count, d_r, d_s, d_d in dev_jobs:
+            Mp, Lp = pools[(P, dt)]
+            S = P * (P + 1)
+            inp, out = (Mp, Lp) if op == "m2l" else ((Mp, Mp) if op == "m2m" else (Lp, Lp))
+            sh.sh_translate_indexed(ctx, op, dt, P, P, count, d_r, d_s, inp, S, d_d, out, S)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    resident_pass()
+    t_resident = resident_pass()
     del dev_jobs
     ntr = sum(len(j[4]) for j in jobs)
     sat["plain_device_resident_s"] = round(t_resident, 4)
@@ -443,11 +462,13 @@ def run_fmm(sh, ctx, torch, dev, P=10, levels=4, npts=64, reps=3):
 
 def time_launch(torch, fn, reps):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
-    (the stream the library launches on by default)."""
-    fn()
+    (the stream the library launches on by default).  The start event is queued behind an
+    untimed warm-up launch, so the device is still busy with it while the host issues the
+    timed launches: the host's time to issue the first one is not counted."""
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    fn()
     e0.record()
     for _ in range(reps):
         fn()

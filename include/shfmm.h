@@ -166,7 +166,9 @@ typedef struct sh_plan sh_plan; /* opaque: a work list binned and uploaded for e
 /* Bins a HOST array of `count` items by operation and order and uploads it (synchronous;
  * allocates device memory owned by the plan).  Items of orders <= 16 run on the
  * lane-per-translation kernel (64 translations per workgroup, orders rounded up to a
- * bucket), larger orders on the one-wavefront-per-translation kernel; SH_PLAN_AUTOTUNE
+ * bucket), orders 17..31 on the block kernel (16 translations of one operation and order
+ * pair per task, FP64 matrix cores; classes up to 20, 24 and 31) and larger orders on the
+ * one-wavefront-per-translation kernel; SH_PLAN_AUTOTUNE
  * times the candidate mappings of each bin on zero-filled scratch arenas and keeps the
  * fastest (decisions are cached per process and, when the environment variable
  * SHFMM_TUNE_FILE names a file, in that file).  flags: SH_ACCUMULATE, SH_PLAN_AUTOTUNE,
@@ -324,8 +326,13 @@ sh_status sh_server_wait(sh_server *server, int64_t job_id, double *latency_s);
 /* Waits until no job is queued or running. */
 sh_status sh_server_drain(sh_server *server);
 
-/* Counters and latency percentiles since creation. */
+/* Counters and latency percentiles since creation or the last sh_server_stats_reset. */
 sh_status sh_server_stats_get(sh_server *server, sh_server_stats *stats);
+
+/* Starts a new statistics window: the counters, the latencies, the staging peak and the
+ * elapsed clock start again from zero (jobs still queued or running are counted in the new
+ * window when they complete).  Errors: SH_EINVAL (NULL server). */
+sh_status sh_server_stats_reset(sh_server *server);
 
 /* ---------------- single translation (host pointers, synchronous) ----------------
  * The paper's statement of the problem: one input solid, one shift, one output solid.

@@ -88,6 +88,7 @@ _SIGS = {
     "sh_server_wait": (_c_i32, [_vp, _c_i64, ctypes.POINTER(ctypes.c_double)]),
     "sh_server_drain": (_c_i32, [_vp]),
     "sh_server_stats_get": (_c_i32, [_vp, _vp]),
+    "sh_server_stats_reset": (_c_i32, [_vp]),
     "sh_translate_single_noalloc": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp]),
 }
 for _op in ("m2l", "m2m", "l2l"):
@@ -522,6 +523,9 @@ class Server:
         _check(lib().sh_server_stats_get(self.handle, ctypes.byref(st)), "sh_server_stats_get")
         return st.as_dict()
 
+    def stats_reset(self):
+        _check(lib().sh_server_stats_reset(self.handle), "sh_server_stats_reset")
+
     def close(self):
         if self._h:
             lib().sh_server_destroy(self._h)
@@ -572,6 +576,10 @@ def sh_server_drain(server: Server) -> None:
 
 def sh_server_stats_get(server: Server) -> dict:
     return server.stats()
+
+
+def sh_server_stats_reset(server: Server) -> None:
+    server.stats_reset()
 
 
 def sh_fmm_create(ctx, P, levels, origin, width, npts):

@@ -110,15 +110,23 @@ struct Tree {
 // this kind share a tree while their destinations are disjoint.
 bool shares_tree(int op, unsigned flags) { return op == SH_M2L && !(flags & SH_ACCUMULATE); }
 
+// A host buffer for a job's packed records, taken from the server's free list and returned
+// to it when the job completes, so that submissions write memory that is already mapped
+// (packing into freshly allocated pages costs several times the packing itself).
+struct Buf {
+    std::unique_ptr<char[]> p;
+    size_t cap = 0;
+};
+
 struct Job {
     int32_t tree = 0, op = 0;
     unsigned flags = 0;
     int64_t count = 0;
-    std::vector<int64_t> dst;   // destination slots (claims of shared trees)
     // packed at submission in the layout a batch stages: the shifts in the tree's dtype
     // (count x 3), then the source and the destination slots as solid indices counted from
     // the start of the pool arena (count each)
-    std::vector<char> packed;
+    Buf packed;
+    int64_t dst_base = 0;       // arena index of the destination pool's slot 0
     int64_t footprint = 0;
     double t_submit = 0, t_done = 0;
     bool done = false;
@@ -139,6 +147,88 @@ struct Batch {
 
 int64_t job_footprint(int64_t count) { return 80 * count + 2048; }
 
+// Copies into the pinned staging, split over a few threads: one thread's memcpy moves a few
+// GB/s, which at saturation falls behind the device.  Pieces of at most kCopyPiece bytes are
+// taken in turn by the caller and kCopyThreads workers; run() returns when all are copied.
+// Only the scheduler thread calls run().
+struct CopySeg {
+    char *dst;
+    const char *src;
+    size_t n;
+};
+constexpr size_t kCopyPiece = 1 << 20;
+constexpr int kCopyThreads = 3;
+
+void add_copy(std::vector<CopySeg> &v, char *dst, const char *src, size_t n)
+{
+    for (size_t o = 0; o < n; o += kCopyPiece) v.push_back(CopySeg{dst + o, src + o, std::min(kCopyPiece, n - o)});
+}
+
+struct CopyPool {
+    std::vector<std::thread> th;
+    std::mutex mu;
+    std::condition_variable cv_go, cv_done;
+    const std::vector<CopySeg> *segs = nullptr;
+    size_t next = 0, left = 0;
+    bool stop = false;
+
+    void worker()
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            cv_go.wait(lk, [&] { return stop || (segs && next < segs->size()); });
+            if (!segs || next >= segs->size()) return;  // stopping, nothing left to copy
+            const CopySeg sg = (*segs)[next++];
+            lk.unlock();
+            std::memcpy(sg.dst, sg.src, sg.n);
+            lk.lock();
+            if (--left == 0) cv_done.notify_all();
+        }
+    }
+    void start()
+    {
+        for (int i = 0; i < kCopyThreads; ++i) th.emplace_back(&CopyPool::worker, this);
+    }
+    void finish()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_go.notify_all();
+        for (auto &t : th)
+            if (t.joinable()) t.join();
+        th.clear();
+    }
+    void run(const std::vector<CopySeg> &v)
+    {
+        if (v.size() <= 1 || th.empty()) {
+            for (const CopySeg &sg : v) std::memcpy(sg.dst, sg.src, sg.n);
+            return;
+        }
+        std::unique_lock<std::mutex> lk(mu);
+        segs = &v;
+        next = 0;
+        left = v.size();
+        cv_go.notify_all();
+        while (next < v.size()) {
+            const CopySeg sg = v[next++];
+            lk.unlock();
+            std::memcpy(sg.dst, sg.src, sg.n);
+            lk.lock();
+            --left;
+        }
+        cv_done.wait(lk, [&] { return left == 0; });
+        segs = nullptr;
+    }
+};
+
+// destination slots of a job (relative to its pool), read back from its packed records
+const int64_t *job_dst_abs(const Job &j, int64_t elem)
+{
+    return reinterpret_cast<const int64_t *>(j.packed.p.get() + (size_t)j.count * (size_t)(3 * elem + 8));
+}
+
 }  // namespace
 
 struct sh_server {
@@ -148,6 +238,11 @@ struct sh_server {
     void *dstage = nullptr;      // device staging (work records)
     void *hstage = nullptr;      // pinned host staging, same offsets
     RangeAlloc pool_alloc, stage_alloc;
+    CopyPool copier;
+    // free pack buffers (returned by completed jobs), at most kKeepBufBytes in all
+    std::mutex buf_mu;
+    std::vector<Buf> bufs;
+    size_t bufs_bytes = 0;
     std::vector<hipStream_t> streams;
     std::vector<std::deque<Batch>> inflight;
     std::vector<std::thread> completers;
@@ -177,6 +272,45 @@ struct sh_server {
 
 namespace {
 
+// Free pack buffers kept for reuse: up to 8x the staging budget (at least 64 MiB) in all.
+size_t keep_buf_bytes(const sh_server *S) { return std::max<size_t>(size_t(64) << 20, 8 * (size_t)S->cfg.staging_bytes); }
+
+// A pack buffer of at least n bytes: the smallest free one that fits, else a new one.
+Buf take_buf(sh_server *S, size_t n)
+{
+    {
+        std::lock_guard<std::mutex> lk(S->buf_mu);
+        size_t best = SIZE_MAX;
+        for (size_t i = 0; i < S->bufs.size(); ++i)
+            if (S->bufs[i].cap >= n && (best == SIZE_MAX || S->bufs[i].cap < S->bufs[best].cap)) best = i;
+        if (best != SIZE_MAX) {
+            Buf b = std::move(S->bufs[best]);
+            if (best + 1 != S->bufs.size()) S->bufs[best] = std::move(S->bufs.back());
+            S->bufs.pop_back();
+            S->bufs_bytes -= b.cap;
+            return b;
+        }
+    }
+    Buf b;
+    b.p.reset(new char[n]);
+    b.cap = n;
+    return b;
+}
+
+// Returns a buffer to the free list (or frees it when the list is full).
+void give_buf(sh_server *S, Buf &&b)
+{
+    if (!b.p) return;
+    Buf drop;
+    std::lock_guard<std::mutex> lk(S->buf_mu);
+    if (S->bufs_bytes + b.cap > keep_buf_bytes(S)) {
+        drop = std::move(b);
+        return;
+    }
+    S->bufs_bytes += b.cap;
+    S->bufs.push_back(std::move(b));
+}
+
 // Reserves (on) or releases (off) a job's claim on its tree: the running count, the tree
 // alone for a job that does not share it, the destination slots for one that does.  Called
 // with the server lock held.
@@ -184,7 +318,8 @@ void reserve_job(Tree &t, const Job &j, bool on)
 {
     t.running += on ? 1 : -1;
     if (shares_tree(j.op, j.flags)) {
-        for (int64_t d : j.dst) t.claim[(size_t)d] = on ? 1 : 0;
+        const int64_t *d = job_dst_abs(j, t.dtype == SH_F32 ? 4 : 8);
+        for (int64_t i = 0; i < j.count; ++i) t.claim[(size_t)(d[i] - j.dst_base)] = on ? 1 : 0;
     } else {
         t.exclusive = on;
     }
@@ -235,18 +370,21 @@ hipError_t launch_batch(sh_server *S, Batch &b)
     if (bytes > b.st_bytes) return hipErrorInvalidValue;  // footprint bound violated (cannot happen)
     char *h = static_cast<char *>(S->hstage) + b.st_off;
     char *d = static_cast<char *>(S->dstage) + b.st_off;
+    std::vector<CopySeg> segs;
     for (auto &g : groups) {
         const int64_t elem = g.dtype == SH_F32 ? 4 : 8;
         int64_t at = 0;
         for (size_t k : g.jobs) {
             const Job &j = *b.jp[k];
             const size_t rb = (size_t)(3 * elem * j.count), ib = (size_t)(8 * j.count);
-            std::memcpy(h + g.r_off + 3 * elem * at, j.packed.data(), rb);
-            std::memcpy(h + g.s_off + 8 * at, j.packed.data() + rb, ib);
-            std::memcpy(h + g.d_off + 8 * at, j.packed.data() + rb + ib, ib);
+            const char *src = j.packed.p.get();
+            add_copy(segs, h + g.r_off + 3 * elem * at, src, rb);
+            add_copy(segs, h + g.s_off + 8 * at, src + rb, ib);
+            add_copy(segs, h + g.d_off + 8 * at, src + rb + ib, ib);
             at += j.count;
         }
     }
+    S->copier.run(segs);
     hipStream_t s = S->streams[b.stream];
     hipError_t e = hipMemcpyAsync(d, h, (size_t)bytes, hipMemcpyHostToDevice, s);
     for (auto &g : groups) {
@@ -289,8 +427,9 @@ void scheduler_main(sh_server *S)
                 bool fits = shared ? !t.exclusive : t.running == 0;
                 if (fits && shared) {
                     if (t.claim.size() != (size_t)t.n_l) t.claim.assign((size_t)t.n_l, 0);
-                    for (int64_t d : j.dst)
-                        if (t.claim[(size_t)d]) {
+                    const int64_t *d = job_dst_abs(j, t.dtype == SH_F32 ? 4 : 8);
+                    for (int64_t i = 0; i < j.count; ++i)
+                        if (t.claim[(size_t)(d[i] - j.dst_base)]) {
                             fits = false;
                             break;
                         }
@@ -387,6 +526,7 @@ void completer_main(sh_server *S, int stream)
             if (e != hipSuccess) j.status = SH_EDEVICE;
             Tree &tr = S->trees.at(j.tree);
             reserve_job(tr, j, false);
+            give_buf(S, std::move(j.packed));
             --tr.pending;
             if (j.status == SH_OK) {
                 S->latencies.push_back(t - j.t_submit);
@@ -464,6 +604,7 @@ sh_status sh_server_create(sh_ctx *ctx, const sh_server_config *cfg, sh_server *
         S->pool_alloc.init(S->cfg.pool_bytes);
         S->stage_alloc.init(S->cfg.staging_bytes);
         S->inflight.resize(S->streams.size());
+        S->copier.start();
         S->scheduler = std::thread(scheduler_main, S);
         for (size_t i = 0; i < S->streams.size(); ++i) S->completers.emplace_back(completer_main, S, (int)i);
         *out = S;
@@ -489,6 +630,7 @@ void sh_server_destroy(sh_server *S)
         S->cv_complete.notify_all();
         for (auto &t : S->completers)
             if (t.joinable()) t.join();
+        S->copier.finish();
         DeviceGuard g(S->ctx->device);
         for (auto s : S->streams) (void)hipStreamDestroy(s);
         if (S->hstage) (void)hipHostFree(S->hstage);
@@ -628,11 +770,24 @@ sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
         const int64_t base_out = j.op == SH_M2M ? t.off_m / sz_m : t.off_l / sz_l;
         // one pass: check and pack every translation; destinations unique within the job
         // (a bit per slot of the destination pool)
-        j.dst.resize(n);
-        j.packed.resize(n * (size_t)(3 * elem + 16));
-        char *pr = j.packed.data();
+        j.dst_base = base_out;
+        if (n > 0) j.packed = take_buf(S, n * (size_t)(3 * elem + 16));
+        char *pr = j.packed.p.get();
         int64_t *ps = reinterpret_cast<int64_t *>(pr + n * 3 * elem), *pd = ps + n;
-        std::vector<uint64_t> mark((size_t)(n_out + 63) / 64, 0);
+        // the bitset is kept per submitting thread and left all zero: on every exit the words
+        // this job marked are cleared again (a fresh zeroed bitset per job costs more than
+        // the check at large pools)
+        thread_local std::vector<uint64_t> mark;
+        if (mark.size() < (size_t)(n_out + 63) / 64) mark.resize((size_t)(n_out + 63) / 64, 0);
+        struct Unmark {
+            std::vector<uint64_t> &m;
+            const int64_t *dst;
+            size_t marked = 0;
+            ~Unmark()
+            {
+                for (size_t i = 0; i < marked; ++i) m[(size_t)dst[i] >> 6] = 0;
+            }
+        } unmark{mark, job->dst};
         for (size_t i = 0; i < n; ++i) {
             const double x = job->r[3 * i], y = job->r[3 * i + 1], z = job->r[3 * i + 2];
             if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return SH_ESHIFT;
@@ -643,6 +798,7 @@ sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
             const uint64_t bit = uint64_t(1) << (dv & 63);
             if (w & bit) return SH_EINVAL;
             w |= bit;
+            unmark.marked = i + 1;
             if (f32) {
                 float *r = reinterpret_cast<float *>(pr) + 3 * i;
                 r[0] = (float)x;
@@ -656,7 +812,6 @@ sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
             }
             ps[i] = base_in + sv;
             pd[i] = base_out + dv;
-            j.dst[i] = dv;
         }
         // for M2M / L2L (one pool) no destination is also a source
         if (j.op != SH_M2L)
@@ -760,6 +915,18 @@ sh_status sh_server_stats_get(sh_server *S, sh_server_stats *st)
     } catch (...) {
         return SH_EDEVICE;
     }
+}
+
+sh_status sh_server_stats_reset(sh_server *S)
+{
+    if (!S) return SH_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->latencies.clear();
+    S->jobs_done = S->translations_done = S->batches = S->batch_jobs = S->failed = S->jobs_deferred = 0;
+    S->queue_peak = (int64_t)S->queue.size();
+    S->stage_alloc.peak = S->stage_alloc.used;
+    S->t_first_submit = S->t_last_done = -1;
+    return SH_OK;
 }
 
 }  // extern "C"

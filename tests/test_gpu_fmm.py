@@ -225,6 +225,27 @@ def test_fmm_graph_replays_match_eager(ctx):
     f.close()
 
 
+def test_fmm_error_is_set_by_the_lowest_level_order(ctx):
+    """The premise of one order for every level: on a uniform 4-level tree the leaf level
+    alone, and the two coarser levels alone, each leave about the error of the uniform choice.
+    Raising the other levels' orders by 2-5 (each order is a factor of about 0.44 in the error)
+    lowers the error by less than 1.7x, so a cheaper leaf order cannot be bought with dearer
+    coarse ones."""
+    levels, npts = 4, 4
+    origin, width = (0.0, 0.0, 0.0), 1.0
+    pts, q = _particles(levels, npts, origin, width, seed=101)
+    exact = _direct(pts, q)[:, 0]
+    err = {}
+    for orders in ((10, 10, 10), (15, 13, 10), (10, 10, 12), (12, 12, 12)):
+        got, _ = _gpu_fmm(ctx, 0, levels, origin, width, pts, q, orders=list(orders))
+        err[orders] = _rel(got[:, 0], exact)
+    print("[fmm] per-level orders", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    uniform = err[(10, 10, 10)]
+    assert err[(15, 13, 10)] > uniform / 1.7   # leaf at 10, coarse levels raised
+    assert err[(10, 10, 12)] > uniform / 1.7   # coarse levels at 10, leaf raised
+    assert err[(12, 12, 12)] < uniform / 2.5   # raising every level does lower it
+
+
 @pytest.mark.parametrize("levels,npts", [(3, 10), (2, 30), (4, 4)], ids=["3x10", "2x30", "4x4"])
 @pytest.mark.parametrize("tol", [1e-3, 1e-5])
 def test_fmm_orders_for_tolerance_meet_target(ctx, tol, levels, npts):

@@ -315,3 +315,37 @@ def test_server_trees_of_one_order_share_a_call(ctx, orc, dtype):
         Cin = from_basis(to_basis(C, P, kind_in, dtype), P, kind_in, dtype)
         out = from_basis(together[k], P, "M" if op == "m2m" else "L", dtype)
         check_job(orc, dtype, op, P, r, Cin[src] if dtype == sh.SH_F64 else C[src], out[dst], f"shared call {op}")
+
+
+def test_server_pack_buffers_reused_and_stats_window(ctx, orc):
+    """Jobs submitted one after another pack into buffers that completed jobs returned (a
+    larger job takes a new buffer, a smaller one a free larger buffer), and jobs whose records
+    are copied to the staging in pieces by several threads (over 1 MiB): every result equals
+    the oracle, and a repeated job equals its first run bit for bit.  stats_reset starts a
+    new statistics window."""
+    P, n = 6, 60000
+    dtype = sh.SH_F64
+    print("[server] pack buffers and stats window", flush=True)
+    srv = sh.Server(ctx, pool_bytes=256 << 20, staging_bytes=16 << 20, streams=2)
+    t, M, L = make_tree(srv, orc, dtype, P, n, 7)
+    Cin = from_basis(to_basis(M, P, "M", dtype), P, "M", dtype)
+    first = {}
+    for k, count in enumerate([5000, 5000, 50000, 3000, 50000, 5000]):
+        r, src, dst = job_arrays("m2l", n, count, 900 + count)
+        srv.wait(srv.submit(t, "m2l", r, src, dst))
+        out, _ = read_pool(srv, t, 1, P, n, dtype)
+        if count in first:
+            assert np.array_equal(out[dst], first[count]), f"job {k} ({count}) differs from its first run"
+        else:
+            check_job(orc, dtype, "m2l", P, r, Cin[src], out[dst], f"pack buffers {count}")
+            first[count] = out[dst].copy()
+    assert srv.stats()["jobs_done"] == 6
+    srv.stats_reset()
+    st = srv.stats()
+    assert st["jobs_done"] == 0 and st["batches"] == 0 and st["translations_done"] == 0
+    assert st["elapsed_s"] == 0.0 and st["p99_s"] == 0.0
+    r, src, dst = job_arrays("m2l", n, 4000, 77)
+    srv.wait(srv.submit(t, "m2l", r, src, dst))
+    st = srv.stats()
+    assert st["jobs_done"] == 1 and st["translations_done"] == 4000 and st["elapsed_s"] > 0
+    srv.close()
