@@ -88,8 +88,10 @@ def check_shared(got, ref, p32, p_out, op, prec, what):
     return check(got, ref, p_out, OUT_KIND[op], TOL_PREC[prec], what, plain32=p32, factor32=PLAIN32_FACTOR)
 
 
+# orders 5..20: 4-real and 2-real input rows, one and several K chunks, and (order 20) output
+# rows that take two chunks of output tiles
 CASES = [("m2l", 8, 8), ("m2l", 10, 10), ("m2l", 7, 12), ("m2l", 16, 16), ("m2m", 10, 10), ("l2l", 10, 10),
-         ("m2m", 6, 9), ("l2l", 12, 5)]
+         ("m2m", 6, 9), ("l2l", 12, 5), ("m2l", 18, 20)]
 
 
 @pytest.mark.parametrize("prec", [sh.SH_SHARED_BF16X6, sh.SH_SHARED_BF16X3, sh.SH_SHARED_FP32], ids=PREC_ID.get)
