@@ -140,6 +140,20 @@ sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, i
                                void *out_pool, int64_t ld_out, unsigned flags,
                                void *hip_stream);
 
+/* Checked form of sh_translate_indexed, for index arrays that are not known to be valid:
+ * n_in and n_out are the numbers of solids in in_pool and out_pool.  The two index arrays
+ * are copied to the host and checked before anything is launched (the call synchronises
+ * the stream and takes host memory for the copies): every src in [0, n_in), every dst in
+ * [0, n_out), no dst repeated under SH_ACCUMULATE, and, when in_pool == out_pool, no dst
+ * that is also a src.  On a violation it returns SH_EINVAL and launches nothing; otherwise
+ * it enqueues the translation as sh_translate_indexed does.  Errors as sh_translate_indexed,
+ * SH_EINVAL also for negative n_in / n_out, SH_EDEVICE if the copies fail. */
+sh_status sh_translate_indexed_checked(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out,
+                                       int64_t count, const void *r, const int64_t *src,
+                                       const void *in_pool, int64_t ld_in, int64_t n_in,
+                                       const int64_t *dst, void *out_pool, int64_t ld_out,
+                                       int64_t n_out, unsigned flags, void *hip_stream);
+
 /* ---------------- mixed work lists (batching across operations and orders) ----------------
  * A work list mixes M2M, M2L and L2L translations of any orders (p_in != p_out allowed) in
  * one call.  Item i reads the input solid at arena_in + items[i].in_off (p_in(p_in+1)

@@ -57,6 +57,8 @@ _SIGS = {
     "sh_device_error": (_c_i32, [_vp]),
     "sh_translate_batch": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
     "sh_translate_indexed": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _vp, _c_i64, _vp, _vp, _c_i64, _c_u32, _vp]),
+    "sh_translate_indexed_checked": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_i64, _vp, _vp, _vp, _c_i64, _c_i64,
+                                              _vp, _vp, _c_i64, _c_i64, _c_u32, _vp]),
     "sh_m2l_naive_batch_f64": (_c_i32, [_vp, _c_i32, _c_i32, _c_i64, _vp, _vp, _c_i64, _vp, _c_i64, _c_u32, _vp]),
     "sh_p2m_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _vp, _c_i64, _vp]),
     "sh_l2p_batch_f64": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _vp, _c_i64, _vp, _c_u32, _vp]),
@@ -224,6 +226,13 @@ def sh_translate_indexed(ctx, op, dtype, p_in, p_out, count, r, src, in_pool, ld
     _check(lib().sh_translate_indexed(_h(ctx), OPS.get(op, op), dtype, p_in, p_out, count, _ptr(r), _ptr(src),
                                       _ptr(in_pool), ld_in, _ptr(dst), _ptr(out_pool), ld_out, flags,
                                       _stream(stream)), "sh_translate_indexed")
+
+
+def sh_translate_indexed_checked(ctx, op, dtype, p_in, p_out, count, r, src, in_pool, ld_in, n_in, dst, out_pool,
+                                 ld_out, n_out, flags=0, stream=None):
+    _check(lib().sh_translate_indexed_checked(_h(ctx), OPS.get(op, op), dtype, p_in, p_out, count, _ptr(r), _ptr(src),
+                                              _ptr(in_pool), ld_in, n_in, _ptr(dst), _ptr(out_pool), ld_out, n_out,
+                                              flags, _stream(stream)), "sh_translate_indexed_checked")
 
 
 def _make_batch(name):

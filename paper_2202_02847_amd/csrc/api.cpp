@@ -414,6 +414,49 @@ sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, i
     }
 }
 
+sh_status sh_translate_indexed_checked(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out, int64_t count,
+                                       const void *r, const int64_t *src, const void *in_pool, int64_t ld_in,
+                                       int64_t n_in, const int64_t *dst, void *out_pool, int64_t ld_out,
+                                       int64_t n_out, unsigned flags, void *hip_stream)
+{
+    if (!ctx || count < 0 || n_in < 0 || n_out < 0) return SH_EINVAL;
+    if (count > 0 && (!src || !dst)) return SH_EINVAL;
+    try {
+        if (count > 0) {
+            DeviceGuard g(ctx->device);
+            if (!g.ok) return SH_EDEVICE;
+            std::vector<int64_t> hs((size_t)count), hd((size_t)count);
+            hipStream_t s = static_cast<hipStream_t>(hip_stream);
+            const size_t bytes = (size_t)count * sizeof(int64_t);
+            if (hipMemcpyAsync(hs.data(), src, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(hd.data(), dst, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return SH_EDEVICE;
+            for (size_t i = 0; i < (size_t)count; ++i)
+                if (hs[i] < 0 || hs[i] >= n_in || hd[i] < 0 || hd[i] >= n_out) return SH_EINVAL;
+            const bool accumulate = (flags & SH_ACCUMULATE) != 0, alias = in_pool == out_pool;
+            if (accumulate || alias) {
+                std::vector<uint64_t> mark((size_t)(n_out + 63) / 64, 0);  // a bit per destination slot
+                for (size_t i = 0; i < (size_t)count; ++i) {
+                    uint64_t &w = mark[(size_t)hd[i] >> 6];
+                    const uint64_t bit = uint64_t(1) << (hd[i] & 63);
+                    if (accumulate && (w & bit)) return SH_EINVAL;
+                    w |= bit;
+                }
+                if (alias)
+                    for (size_t i = 0; i < (size_t)count; ++i)
+                        if (hs[i] < n_out && (mark[(size_t)hs[i] >> 6] >> (hs[i] & 63) & 1u)) return SH_EINVAL;
+            }
+        }
+        return launch(ctx, op, dtype, p_in, p_out, count, r, src, in_pool, ld_in, dst, out_pool, ld_out, flags,
+                      hip_stream);
+    } catch (const std::bad_alloc &) {
+        return SH_ENOMEM;
+    } catch (...) {
+        return SH_EINVAL;
+    }
+}
+
 #define SH_SINGLE(NAME, OP, DT, T)                                                                 \
     sh_status NAME(const sh_ctx *ctx, int p_in, int p_out, const T r[3], const T *C, T *out)       \
     {                                                                                              \

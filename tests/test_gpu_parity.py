@@ -420,3 +420,55 @@ def test_indexed_call_needs_both_index_arrays(ctx):
         assert st == sh.SH_EINVAL
     torch.cuda.synchronize()
     assert bool((y == 5.0).all())
+
+
+def test_indexed_checked_rejects_bad_indices_and_matches_unchecked(ctx):
+    """The checked indexed call refuses, before any launch, an index outside its pool, a
+    repeated destination under SH_ACCUMULATE and (one pool for input and output) a destination
+    that is also a source; a valid call gives the unchecked call's result bit for bit."""
+    torch, dev = torch_dev()
+    P, n_in, n_out, count = 8, 50, 40, 30
+    S = size(P)
+    rng = np.random.default_rng(12)
+    M = torch.from_numpy(rng.normal(size=(n_in, S)) * 1e-2).to(dev)
+    r = torch.from_numpy(wl.random_shifts(rng, count, 2.0, 6.0)).to(dev)
+    src = rng.integers(0, n_in, count)
+    dst = rng.permutation(n_out)[:count]
+    d_src = torch.from_numpy(src.astype(np.int64)).to(dev)
+    d_dst = torch.from_numpy(dst.astype(np.int64)).to(dev)
+
+    def run(s, d, n_o=n_out, flags=0, out=None, n_i=n_in, inp=M):
+        out = torch.full((n_o, S), 7.0, dtype=torch.float64, device=dev) if out is None else out
+        sh.sh_translate_indexed_checked(ctx, "m2l", sh.SH_F64, P, P, count, r, s, inp, S, n_i, d, out, S, n_o, flags)
+        torch.cuda.synchronize()
+        return out
+
+    got = run(d_src, d_dst)
+    ref = torch.full((n_out, S), 7.0, dtype=torch.float64, device=dev)
+    sh.sh_translate_indexed(ctx, "m2l", sh.SH_F64, P, P, count, r, d_src, M, S, d_dst, ref, S)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    bad = [(np.where(np.arange(count) == 3, n_in, src), dst, 0),       # source past the pool
+           (src, np.where(np.arange(count) == 5, -1, dst), 0),         # negative destination
+           (src, np.where(np.arange(count) == 7, n_out, dst), 0),      # destination past the pool
+           (src, np.where(np.arange(count) == 9, dst[0], dst), sh.SH_ACCUMULATE)]  # repeated, accumulating
+    for s_, d_, fl in bad:
+        out = torch.full((n_out, S), 7.0, dtype=torch.float64, device=dev)
+        with pytest.raises(sh.ShError) as e:
+            run(torch.from_numpy(s_.astype(np.int64)).to(dev), torch.from_numpy(d_.astype(np.int64)).to(dev),
+                flags=fl, out=out)
+        assert e.value.status == sh.SH_EINVAL
+        torch.cuda.synchronize()
+        assert bool((out == 7.0).all())
+    # one pool for input and output: a destination that is also a source is refused
+    pool = torch.from_numpy(rng.normal(size=(n_in, S)) * 1e-2).to(dev)
+    keep = pool.clone()
+    s_al = np.arange(count, dtype=np.int64)
+    d_al = np.arange(count, dtype=np.int64) + 10  # overlaps sources 10..29
+    with pytest.raises(sh.ShError) as e:
+        sh.sh_translate_indexed_checked(ctx, "m2m", sh.SH_F64, P, P, count, r,
+                                        torch.from_numpy(s_al).to(dev), pool, S, n_in,
+                                        torch.from_numpy(d_al).to(dev), pool, S, n_in)
+    assert e.value.status == sh.SH_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(pool, keep)
