@@ -619,7 +619,7 @@ def run_section(sh, ctx, torch, dev, name, args):
         log("[bench] L2P P=10")
         out["l2p_p10_f64"] = run_l2p(sh, ctx, torch, dev)
     elif name == "orders":
-        for PP, nn_ in ((16, 1 << 20), (30, 1 << 18)):
+        for PP, nn_ in ((16, 1 << 20), (20, 1 << 18), (24, 1 << 18), (30, 1 << 18)):
             log(f"[bench] extra P={PP} n={nn_}")
             J = make_octree_inputs(sh, ctx, torch, dev, PP, nn_)
             SS = solid(PP)
