@@ -183,7 +183,10 @@ typedef struct sh_plan sh_plan; /* opaque: a work list binned and uploaded for e
  * bucket), orders 17..31 on the block kernel (16 translations of one operation and order
  * pair per task, FP64 matrix cores; classes up to 20, 24 and 31) and larger orders on the
  * one-wavefront-per-translation kernel; SH_PLAN_AUTOTUNE
- * times the candidate mappings of each bin on zero-filled scratch arenas and keeps the
+ * times the candidate mappings of each bin on zero-filled scratch arenas (orders up to 16:
+ * 64- or 32-translation tasks or one wavefront per translation; orders 17..31: the block
+ * kernel in workgroups of 4 wavefronts two per CU or of 8 one per CU, or one wavefront per
+ * translation) and keeps the
  * fastest (decisions are cached per process and, when the environment variable
  * SHFMM_TUNE_FILE names a file, in that file).  flags: SH_ACCUMULATE, SH_PLAN_AUTOTUNE,
  * SH_PLAN_NO_GRAPH.  Errors: SH_EINVAL (null pointers, unknown op/dtype/flags, reserved

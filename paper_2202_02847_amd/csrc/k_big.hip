@@ -672,29 +672,33 @@ hipError_t launch_big_list_nw(const DevTables &tab, const ListArgs &la, int pmax
     return hipGetLastError();
 }
 
+// workgroups of 4 wavefronts (two per CU) where asked for and two blocks' LDS fit, else of 8
 template <typename Real, int OP>
-hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pmax, hipStream_t s)
+hipError_t launch_big_list_one(const DevTables &tab, const ListArgs &la, int pmax, int nw, hipStream_t s)
 {
-    return big_two_per_cu(pmax) ? launch_big_list_nw<Real, OP, 4>(tab, la, pmax, s)
-                                : launch_big_list_nw<Real, OP, 8>(tab, la, pmax, s);
+    return nw == 4 && big_two_per_cu(pmax) ? launch_big_list_nw<Real, OP, 4>(tab, la, pmax, s)
+                                           : launch_big_list_nw<Real, OP, 8>(tab, la, pmax, s);
 }
 
 template <typename Real>
-hipError_t launch_big_list_op(const DevTables &tab, const ListArgs &la, int op, int pmax, hipStream_t s)
+hipError_t launch_big_list_op(const DevTables &tab, const ListArgs &la, int op, int pmax, int nw, hipStream_t s)
 {
-    if (op == OP_M2M) return launch_big_list_one<Real, OP_M2M>(tab, la, pmax, s);
-    if (op == OP_M2L) return launch_big_list_one<Real, OP_M2L>(tab, la, pmax, s);
-    return launch_big_list_one<Real, OP_L2L>(tab, la, pmax, s);
+    if (op == OP_M2M) return launch_big_list_one<Real, OP_M2M>(tab, la, pmax, nw, s);
+    if (op == OP_M2L) return launch_big_list_one<Real, OP_M2L>(tab, la, pmax, nw, s);
+    return launch_big_list_one<Real, OP_L2L>(tab, la, pmax, nw, s);
 }
 
 }  // namespace
 
-hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, hipStream_t s)
+hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, int nw, hipStream_t s)
 {
     if (la.ntasks <= 0) return hipSuccess;
     if (pmax < 1 || pmax >= kBigOrder) return hipErrorInvalidValue;
-    return f32 ? launch_big_list_op<float>(tab, la, op, pmax, s) : launch_big_list_op<double>(tab, la, op, pmax, s);
+    return f32 ? launch_big_list_op<float>(tab, la, op, pmax, nw, s)
+               : launch_big_list_op<double>(tab, la, op, pmax, nw, s);
 }
+
+bool big_list_two_per_cu(int pmax) { return pmax >= 1 && pmax < kBigOrder && big_two_per_cu(pmax); }
 
 bool big_available(int p_in, int p_out)
 {

@@ -104,7 +104,10 @@ size_t big_lds_bytes(int PM);
 hipError_t launch_big(const DevTables &tab, const TransArgs &a, bool f32, hipStream_t s);
 // Work-list form: tasks of up to 16 items of operation op sharing (p_in, p_out); pmax = the
 // largest order of the launch's tasks (sizes the LDS), below 32.
-hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, hipStream_t s);
+// nw: 4 for workgroups of 4 wavefronts, two per CU (used only where two blocks' LDS fit,
+// big_list_two_per_cu), else one workgroup of 8 per CU
+hipError_t launch_list_big(const DevTables &tab, const ListArgs &la, int op, bool f32, int pmax, int nw, hipStream_t s);
+bool big_list_two_per_cu(int pmax);
 
 // Highest order with a fixed-order (lane-per-translation) kernel.
 constexpr int kLptMaxOrder = 16;

@@ -34,6 +34,7 @@ using shfmm::ListItem;
 using shfmm::ListTask;
 using shfmm::ListBin;
 using shfmm::MAP_BLOCK;
+using shfmm::MAP_BLOCK8;
 using shfmm::MAP_GENERAL;
 using shfmm::MAP_LPT32;
 using shfmm::MAP_LPT64;
@@ -47,7 +48,11 @@ namespace {
 
 const char *mapping_name(int m)
 {
-    return m == MAP_LPT64 ? "lpt64" : m == MAP_LPT32 ? "lpt32" : m == MAP_BLOCK ? "block" : "wave";
+    return m == MAP_LPT64   ? "lpt64"
+           : m == MAP_LPT32 ? "lpt32"
+           : m == MAP_BLOCK ? "block"
+           : m == MAP_BLOCK8 ? "block8"
+                             : "wave";
 }
 
 int64_t solid_reals(int p) { return (int64_t)p * (p + 1); }
@@ -87,7 +92,7 @@ void tune_load_locked()
     int d, o, b, c, m;
     char line[256];
     while (std::fgets(line, sizeof line, fp))
-        if (std::sscanf(line, "%d %d %d %d %d", &d, &o, &b, &c, &m) == 5 && m >= 0 && m <= 2)
+        if (std::sscanf(line, "%d %d %d %d %d", &d, &o, &b, &c, &m) == 5 && m >= 0 && m <= MAP_BLOCK8)
             g_tune[TuneKey{d, o, b, c}] = m;
     std::fclose(fp);
 }
@@ -169,7 +174,8 @@ hipError_t shfmm::launch_list_bin(const sh_ctx *ctx, bool f32, const ListBin &b,
     la.flags = flags & SH_ACCUMULATE;
     la.err = ctx->err_flag;
     if (b.mapping == MAP_GENERAL) return shfmm::launch_list_general(ctx->tabs, la, f32, b.wide, b.pmax, s);
-    if (b.mapping == MAP_BLOCK) return shfmm::launch_list_big(ctx->tabs, la, b.op, f32, b.pmax, s);
+    if (shfmm::is_block(b.mapping))
+        return shfmm::launch_list_big(ctx->tabs, la, b.op, f32, b.pmax, b.mapping == MAP_BLOCK ? 4 : 8, s);
     return shfmm::launch_list_lpt(ctx->tabs, la, b.op, f32, b.bucket, s);
 }
 
@@ -215,7 +221,7 @@ float time_mapping(const sh_ctx *ctx, bool f32, const ListBin &proto, const std:
     b.item_first = 0;
     b.item_count = (int64_t)it.size();
     std::vector<ListTask> tk;
-    lay_out_bin(b, it, tk, mapping == MAP_LPT32 ? 32 : 64);
+    lay_out_bin(b, it, tk, shfmm::task_size(mapping));
     DeviceLists dl;
     if (dl.upload(it, tk) != hipSuccess) return -1;
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
@@ -349,18 +355,30 @@ sh_status plan_build(sh_ctx *ctx, int dtype, const sh_item *items, int64_t count
         return SH_EDEVICE;
     auto choose = [&](ListBin &b, const std::vector<ListItem> &v) -> int {
         bool tuned = false;
-        int m = shfmm::cached_mapping(dtype, b.op, b.bucket, (int64_t)v.size(), &tuned);
+        const bool block = shfmm::is_block(b.mapping);
+        int m = shfmm::cached_mapping(dtype, b.op, b.bucket, (int64_t)v.size(), &tuned, b.mapping);
+        if (tuned && block && m == MAP_BLOCK && !shfmm::big_list_two_per_cu(b.pmax)) m = MAP_BLOCK8;
         if (tuned || !(flags & SH_PLAN_AUTOTUNE)) {
             b.tuned = tuned;
             return m;
         }
+        // candidates: the lane-per-translation task sizes and the wavefront kernel for orders
+        // up to 16; the block kernel in both workgroup shapes (where two blocks' LDS fit) and
+        // the wavefront kernel above
+        std::vector<int> cands;
+        if (!block)
+            cands = {MAP_LPT64, MAP_LPT32, MAP_GENERAL};
+        else if (shfmm::big_list_two_per_cu(b.pmax))
+            cands = {MAP_BLOCK, MAP_BLOCK8, MAP_GENERAL};
+        else
+            cands = {MAP_BLOCK8, MAP_GENERAL};
         // a strided sample keeps the mix of orders of the bin
         const size_t kSample = 1 << 15;
         std::vector<ListItem> sample;
         const size_t stride = v.size() > kSample ? (v.size() + kSample - 1) / kSample : 1;
         for (size_t i = 0; i < v.size(); i += stride) sample.push_back(v[i]);
         float best = -1;
-        for (int cand : {MAP_LPT64, MAP_LPT32, MAP_GENERAL}) {
+        for (int cand : cands) {
             const float ms = time_mapping(ctx, f32, b, sample, cand, flags, ts);
             if (ms < 0) return -1;
             if (best < 0 || ms < best) {
@@ -523,7 +541,11 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         if (std::get<0>(g.first) == 1) {
             b.mapping = MAP_GENERAL;
         } else if (std::get<0>(g.first) == 2) {
-            b.mapping = MAP_BLOCK;
+            b.mapping = shfmm::big_list_two_per_cu(b.pmax) ? MAP_BLOCK : MAP_BLOCK8;  // default
+            b.wide = f32 && b.pmax >= shfmm::kF32WideOrder;  // should the wavefront kernel take it
+            const int m = choose(b, v);
+            if (m < 0) return SH_EDEVICE;
+            b.mapping = m;
         } else {
             const int m = choose(b, v);
             if (m < 0) return SH_EDEVICE;
@@ -533,7 +555,7 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
         b.item_count = (int64_t)v.size();
         list.insert(list.end(), v.begin(), v.end());
         std::vector<ListItem>().swap(v);
-        lay_out_bin(b, list, tasks, b.mapping == MAP_LPT32 ? 32 : b.mapping == MAP_BLOCK ? 16 : 64);
+        lay_out_bin(b, list, tasks, shfmm::task_size(b.mapping));
         made.push_back(b);
     }
     // largest bins first, so that their persistent grids start first on the device
@@ -544,12 +566,12 @@ sh_status shfmm::bin_items(int dtype, std::vector<ListItem> &list, std::vector<L
     return SH_OK;
 }
 
-int shfmm::cached_mapping(int dtype, int op, int bucket, int64_t count, bool *tuned)
+int shfmm::cached_mapping(int dtype, int op, int bucket, int64_t count, bool *tuned, int dflt)
 {
-    int m = MAP_LPT64;
+    int m = dflt;
     const bool hit = tune_lookup(TuneKey{dtype, op, bucket, count_class(count)}, &m);
     if (tuned) *tuned = hit;
-    return hit ? m : MAP_LPT64;
+    return hit ? m : dflt;
 }
 
 extern "C" {

@@ -186,12 +186,18 @@ def test_list_graph_replays(ctx, orc):
     pe.close()
 
 
-def test_list_autotune(ctx, orc):
-    """Tuned plans choose a mapping per lane-per-translation bin and stay within the bound."""
+@pytest.mark.parametrize("pmax,lo", [(16, 3), (30, 17)], ids=["lpt-orders", "block-orders"])
+def test_list_autotune(ctx, orc, pmax, lo):
+    """Tuned plans choose a mapping per bin (task size or wavefront kernel up to order 16;
+    block-kernel workgroup shape or wavefront kernel for orders 17..30) and stay within the
+    bound."""
     dtype = sh.SH_F64
-    op, p_in, p_out, r, C = make_list(orc, 300, 31, pmax=16, lo=3)
+    op, p_in, p_out, r, C = make_list(orc, 300, 31 + pmax, pmax=pmax, lo=lo)
     got, _, desc = run_list(ctx, dtype, op, p_in, p_out, r, C, sh.SH_PLAN_AUTOTUNE)
+    print("[list] tuned bins", [(b["mapping"], b["op"], b["items"]) for b in desc["bins"]], flush=True)
     assert desc["bins"] and all(b["tuned"] for b in desc["bins"] if b["op"] != "mixed")
+    if lo > 16:
+        assert all(b["mapping"] in ("block", "block8", "wave") for b in desc["bins"])
     check_items(orc, dtype, op, p_in, p_out, r, C, got, "tuned")
 
 
