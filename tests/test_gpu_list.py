@@ -196,8 +196,10 @@ def test_list_autotune(ctx, orc, pmax, lo):
     got, _, desc = run_list(ctx, dtype, op, p_in, p_out, r, C, sh.SH_PLAN_AUTOTUNE)
     print("[list] tuned bins", [(b["mapping"], b["op"], b["items"]) for b in desc["bins"]], flush=True)
     assert desc["bins"] and all(b["tuned"] for b in desc["bins"] if b["op"] != "mixed")
+    big = [b for b in desc["bins"] if b["pmax"] > 16]
+    assert all(b["mapping"] in ("block", "block8", "wave") for b in big)
     if lo > 16:
-        assert all(b["mapping"] in ("block", "block8", "wave") for b in desc["bins"])
+        assert big
     check_items(orc, dtype, op, p_in, p_out, r, C, got, "tuned")
 
 
