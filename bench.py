@@ -742,12 +742,12 @@ def main():
         d_M32 = (d_M * w).float()
         d_r32 = d_r.float()
         d_L32 = torch.empty((n, S), dtype=torch.float32, device=dev)
-        t = time_launch(torch, lambda: sh.sh_m2l_batch_f32(ctx, P, P, n, d_r32, d_M32, S, d_L32, S), 5)
+        t = time_launch(torch, lambda: sh.sh_m2l_batch_f32(ctx, P, P, n, d_r32, d_M32, S, d_L32, S), 20)
         extra["m2l_p10_f32_per_s"] = n / t
         extra["m2l_p10_f32_frac_hbm"] = bytes_per_translation(P, P, 4) * n / t / 1e9 / HBM_PEAK_GBS
         del d_M32, d_L32
         # single-height M2L (eq. m2lkernels, left) on the same batch
-        t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, P, P, n, d_r, d_M, S, d_L, S, sh.SH_SINGLE_HEIGHT), 5)
+        t = time_launch(torch, lambda: sh.sh_m2l_batch_f64(ctx, P, P, n, d_r, d_M, S, d_L, S, sh.SH_SINGLE_HEIGHT), 20)
         extra["m2l_p10_single_height_f64_per_s"] = n / t
         extra["m2l_p10_single_height_f64_frac_hbm"] = bytes_per_translation(P, P, 8) * n / t / 1e9 / HBM_PEAK_GBS
         nv = 1 << 16
