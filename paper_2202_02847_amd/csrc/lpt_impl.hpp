@@ -35,7 +35,7 @@ __device__ __forceinline__ void static_for(F &&f)
 // least-loaded of the NW wavefronts.  cost(i) ~ (i+1)^2 for rows, (P-m)^2 for columns.
 constexpr int row_owner(int P, int n, int NW = 4)
 {
-    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long load[16] = {};
     int own = 0;
     for (int k = P - 1; k >= 0; --k) {
         int w = 0;
@@ -49,7 +49,7 @@ constexpr int row_owner(int P, int n, int NW = 4)
 
 constexpr int col_owner(int PIN, int POUT, int m, int NW = 4)
 {
-    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long load[16] = {};
     int own = 0;
     const int PM = PIN > POUT ? PIN : POUT;
     for (int k = 0; k < PM; ++k) {
@@ -339,27 +339,22 @@ __device__ __forceinline__ void swap_row_x(cptr<Acc> T, const Acc (&xr)[N + 1], 
 
 // Calls f(std::integral_constant<int, W>) for the wavefront index W = wave, so that each
 // wavefront runs straight-line code for its own share of rows / columns.
+template <int NW, int W, typename F>
+__device__ __forceinline__ void per_wave_from(int wave, F &&f)
+{
+    if constexpr (W == NW - 1) {
+        f(std::integral_constant<int, W>{});
+    } else {
+        if (wave == W)
+            f(std::integral_constant<int, W>{});
+        else
+            per_wave_from<NW, W + 1>(wave, f);
+    }
+}
 template <int NW = 4, typename F>
 __device__ __forceinline__ void per_wave(int wave, F &&f)
 {
-    if (wave == 0)
-        f(std::integral_constant<int, 0>{});
-    else if (wave == 1)
-        f(std::integral_constant<int, 1>{});
-    else if (wave == 2)
-        f(std::integral_constant<int, 2>{});
-    else if (NW == 4 || wave == 3)
-        f(std::integral_constant<int, 3>{});
-    else if constexpr (NW == 8) {
-        if (wave == 4)
-            f(std::integral_constant<int, 4>{});
-        else if (wave == 5)
-            f(std::integral_constant<int, 5>{});
-        else if (wave == 6)
-            f(std::integral_constant<int, 6>{});
-        else
-            f(std::integral_constant<int, 7>{});
-    }
+    per_wave_from<NW, 0>(wave, f);
 }
 
 template <typename Acc>
@@ -392,17 +387,20 @@ constexpr int lpt_min_waves()
 {
     return lpt_blocks_per_cu<Acc, PM>() >= 2 ? 2 : 1;
 }
-// wavefronts per workgroup: 8 (two per SIMD, to hide each other's latency) where LDS allows
-// only one workgroup per CU, else 4
+// wavefronts per workgroup: where LDS allows only one workgroup per CU, 12 (three per SIMD,
+// to hide each other's latency) up to order 14 and 8 (two per SIMD) above, where three per
+// SIMD leave too few registers (2^20 FP64 M2L on one MI355X, 12 against 8 wavefronts:
+// P = 13 0.851 vs 0.889 ms, P = 14 1.050 vs 1.107 ms, P = 15 1.344 vs 1.232 ms, P = 16 1.606
+// vs 1.487 ms); else 4
 template <typename Acc, int PM>
 constexpr int lpt_waves()
 {
-    return lpt_blocks_per_cu<Acc, PM>() >= 2 ? 4 : 8;
+    return lpt_blocks_per_cu<Acc, PM>() >= 2 ? 4 : (PM <= 14 ? 12 : 8);
 }
 template <typename Acc, int PM>
 constexpr int lpt_min_waves_nw()
 {
-    return lpt_blocks_per_cu<Acc, PM>() >= 2 || lpt_waves<Acc, PM>() == 8 ? 2 : 1;
+    return lpt_waves<Acc, PM>() == 12 ? 3 : (lpt_blocks_per_cu<Acc, PM>() >= 2 || lpt_waves<Acc, PM>() == 8 ? 2 : 1);
 }
 // Powers held in registers (tabulated once per block) up to this order, regenerated per row
 // above.  FP32 from order 9 on regenerates them: with the next block's prefetch also off
@@ -484,7 +482,7 @@ void k_lpt(DevTables tab, TransArgs a)
     // the other wavefronts' arithmetic.  (Storing the output rows straight from the
     // backward rotation as well measured no faster than the coalesced store phase, and
     // non-temporal per-lane row stores were 2.5x slower: partial-line writes.)
-    constexpr bool DIRECT = NW == 8;
+    constexpr bool DIRECT = NW >= 8;
     constexpr bool PREFETCH = !DIRECT && LIT * 2 * (int)sizeof(Real) / 4 <= 64 && lpt_prefetch_ok<Real, PM>();
     constexpr int CH = PREFETCH ? LIT : 16 * 4 / (int)sizeof(Real);  // loads per batch
     R2 pre[CH];
