@@ -460,12 +460,20 @@ def run_fmm(sh, ctx, torch, dev, P=10, levels=4, npts=64, reps=3):
             "l2l_per_eval": d["l2l"], "translation_calls": d["calls"]}
 
 
-def time_launch(torch, fn, reps):
+def time_launch(torch, fn, reps, warm_ms=30.0):
     """Average duration of fn() over reps launches, HIP events on torch's current stream
-    (the stream the library launches on by default).  The start event is queued behind an
-    untimed warm-up launch, so the device is still busy with it while the host issues the
-    timed launches: the host's time to issue the first one is not counted."""
+    (the stream the library launches on by default).  Untimed launches of fn run first until
+    the device has been busy warm_ms (after the host-side setup between measurements the device
+    runs the first 10-30 ms of work at a lower clock), and the start event is queued behind the
+    last of them, so the device is still busy while the host issues the timed launches."""
     torch.cuda.synchronize()
+    t_w = time.perf_counter()
+    while True:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t_w >= warm_ms / 1e3:
+            break
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     fn()
