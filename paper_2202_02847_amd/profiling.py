@@ -11,6 +11,11 @@ plain 1 GiB copy that the counter program runs first.
 
 writes the per-launch fetch/write bytes, the scale factors and a hash of the kernel
 sources; bench.py reports the traffic only while that hash matches the current sources.
+
+    python -m paper_2202_02847_amd.profiling last --trace T_kernel_trace.csv --kernel NAME --last 10
+
+gives the mean duration of the last dispatches of a kernel in a kernel trace (the launches at
+the device's steady clock).
 """
 from __future__ import annotations
 
@@ -66,9 +71,26 @@ def traffic(fetch_csv, write_csv, kernel, bytes_per_launch=None):
     return out
 
 
+def last_dispatches(trace_csv, kernel, last):
+    """Mean, min and max duration (us) of the last `last` dispatches of a kernel in a
+    rocprofv3 kernel-trace file: the launches after the device reached its steady clock (the
+    first 10-30 ms of work after idle run at a lower clock)."""
+    rows = [r for r in _read(trace_csv) if kernel in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit(f"kernel {kernel!r} not found in {trace_csv}")
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-last:]]
+    return {"kernel": kernel, "dispatches": len(rows), "last": len(d), "mean_us": sum(d) / len(d),
+            "min_us": min(d), "max_us": max(d)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    lt = sub.add_parser("last")
+    lt.add_argument("--trace", required=True)
+    lt.add_argument("--kernel", required=True)
+    lt.add_argument("--last", type=int, default=10)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -79,6 +101,9 @@ def main():
     args = ap.parse_args()
     if args.cmd == "hash":
         print(kernel_source_hash())
+        return
+    if args.cmd == "last":
+        print(json.dumps(last_dispatches(args.trace, args.kernel, args.last), indent=1))
         return
     res = traffic(args.fetch, args.write, args.kernel, args.bytes_per_launch)
     with open(args.out, "w") as fh:
