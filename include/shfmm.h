@@ -144,10 +144,12 @@ sh_status sh_translate_indexed(const sh_ctx *ctx, int op, int dtype, int p_in, i
  * n_in and n_out are the numbers of solids in in_pool and out_pool.  The two index arrays
  * are copied to the host and checked before anything is launched (the call synchronises
  * the stream and takes host memory for the copies): every src in [0, n_in), every dst in
- * [0, n_out), no dst repeated under SH_ACCUMULATE, and, when in_pool == out_pool, no dst
- * that is also a src.  On a violation it returns SH_EINVAL and launches nothing; otherwise
- * it enqueues the translation as sh_translate_indexed does.  Errors as sh_translate_indexed,
- * SH_EINVAL also for negative n_in / n_out, SH_EDEVICE if the copies fail. */
+ * [0, n_out), no dst repeated under SH_ACCUMULATE, and, when in_pool == out_pool (which
+ * then requires ld_in == ld_out), no dst that is also a src.  Pools given by different
+ * pointers are taken to be disjoint.  On a violation it returns SH_EINVAL and launches
+ * nothing; otherwise it enqueues the translation as sh_translate_indexed does.  Errors as
+ * sh_translate_indexed, SH_EINVAL also for negative n_in / n_out, SH_EDEVICE if the copies
+ * fail. */
 sh_status sh_translate_indexed_checked(const sh_ctx *ctx, int op, int dtype, int p_in, int p_out,
                                        int64_t count, const void *r, const int64_t *src,
                                        const void *in_pool, int64_t ld_in, int64_t n_in,

@@ -435,6 +435,7 @@ sh_status sh_translate_indexed_checked(const sh_ctx *ctx, int op, int dtype, int
             for (size_t i = 0; i < (size_t)count; ++i)
                 if (hs[i] < 0 || hs[i] >= n_in || hd[i] < 0 || hd[i] >= n_out) return SH_EINVAL;
             const bool accumulate = (flags & SH_ACCUMULATE) != 0, alias = in_pool == out_pool;
+            if (alias && ld_in != ld_out) return SH_EINVAL;  // slot indices would not name the same solids
             if (accumulate || alias) {
                 std::vector<uint64_t> mark((size_t)(n_out + 63) / 64, 0);  // a bit per destination slot
                 for (size_t i = 0; i < (size_t)count; ++i) {

@@ -122,9 +122,9 @@ struct Job {
     int32_t tree = 0, op = 0;
     unsigned flags = 0;
     int64_t count = 0;
-    // packed at submission in the layout a batch stages: the shifts in the tree's dtype
-    // (count x 3), then the source and the destination slots as solid indices counted from
-    // the start of the pool arena (count each)
+    // packed at submission: the source and the destination slots as solid indices counted
+    // from the start of the pool arena (count each, so both stay 8-byte aligned), then the
+    // shifts in the tree's dtype (count x 3)
     Buf packed;
     int64_t dst_base = 0;       // arena index of the destination pool's slot 0
     int64_t footprint = 0;
@@ -224,9 +224,9 @@ struct CopyPool {
 };
 
 // destination slots of a job (relative to its pool), read back from its packed records
-const int64_t *job_dst_abs(const Job &j, int64_t elem)
+const int64_t *job_dst_abs(const Job &j)
 {
-    return reinterpret_cast<const int64_t *>(j.packed.p.get() + (size_t)j.count * (size_t)(3 * elem + 8));
+    return reinterpret_cast<const int64_t *>(j.packed.p.get()) + j.count;
 }
 
 }  // namespace
@@ -318,7 +318,7 @@ void reserve_job(Tree &t, const Job &j, bool on)
 {
     t.running += on ? 1 : -1;
     if (shares_tree(j.op, j.flags)) {
-        const int64_t *d = job_dst_abs(j, t.dtype == SH_F32 ? 4 : 8);
+        const int64_t *d = job_dst_abs(j);
         for (int64_t i = 0; i < j.count; ++i) t.claim[(size_t)(d[i] - j.dst_base)] = on ? 1 : 0;
     } else {
         t.exclusive = on;
@@ -378,9 +378,9 @@ hipError_t launch_batch(sh_server *S, Batch &b)
             const Job &j = *b.jp[k];
             const size_t rb = (size_t)(3 * elem * j.count), ib = (size_t)(8 * j.count);
             const char *src = j.packed.p.get();
-            add_copy(segs, h + g.r_off + 3 * elem * at, src, rb);
-            add_copy(segs, h + g.s_off + 8 * at, src + rb, ib);
-            add_copy(segs, h + g.d_off + 8 * at, src + rb + ib, ib);
+            add_copy(segs, h + g.s_off + 8 * at, src, ib);
+            add_copy(segs, h + g.d_off + 8 * at, src + ib, ib);
+            add_copy(segs, h + g.r_off + 3 * elem * at, src + 2 * ib, rb);
             at += j.count;
         }
     }
@@ -427,7 +427,7 @@ void scheduler_main(sh_server *S)
                 bool fits = shared ? !t.exclusive : t.running == 0;
                 if (fits && shared) {
                     if (t.claim.size() != (size_t)t.n_l) t.claim.assign((size_t)t.n_l, 0);
-                    const int64_t *d = job_dst_abs(j, t.dtype == SH_F32 ? 4 : 8);
+                    const int64_t *d = job_dst_abs(j);
                     for (int64_t i = 0; i < j.count; ++i)
                         if (t.claim[(size_t)(d[i] - j.dst_base)]) {
                             fits = false;
@@ -772,8 +772,8 @@ sh_status sh_server_submit(sh_server *S, const sh_job *job, int64_t *job_id)
         // (a bit per slot of the destination pool)
         j.dst_base = base_out;
         if (n > 0) j.packed = take_buf(S, n * (size_t)(3 * elem + 16));
-        char *pr = j.packed.p.get();
-        int64_t *ps = reinterpret_cast<int64_t *>(pr + n * 3 * elem), *pd = ps + n;
+        int64_t *ps = reinterpret_cast<int64_t *>(j.packed.p.get()), *pd = ps + n;
+        char *pr = reinterpret_cast<char *>(pd + n);
         // the bitset is kept per submitting thread and left all zero: on every exit the words
         // this job marked are cleared again (a fresh zeroed bitset per job costs more than
         // the check at large pools)

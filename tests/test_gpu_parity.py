@@ -472,3 +472,12 @@ def test_indexed_checked_rejects_bad_indices_and_matches_unchecked(ctx):
     assert e.value.status == sh.SH_EINVAL
     torch.cuda.synchronize()
     assert torch.equal(pool, keep)
+    # one pool read and written with two strides: the slot indices name different solids,
+    # so the call is refused even with disjoint indices
+    with pytest.raises(sh.ShError) as e:
+        sh.sh_translate_indexed_checked(ctx, "m2m", sh.SH_F64, P, P, 5, r,
+                                        torch.from_numpy(s_al[:5]).to(dev), pool, S, n_in // 2,
+                                        torch.from_numpy(s_al[5:10]).to(dev), pool, 2 * S, n_in // 2)
+    assert e.value.status == sh.SH_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(pool, keep)
