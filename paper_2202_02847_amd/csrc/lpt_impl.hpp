@@ -286,8 +286,10 @@ __device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M], 
 //   Re y = D F^T D^{-1} Re x,   Im y = G^T Im x,
 // computed as updates y += x_L * (packed row L of F, G) over L = 0..N: every output sums its
 // terms in the same (ascending) order as the product with the L-side table would, and the
-// factors 2 and 1/2 are exact, so the result is that product's.  One table then serves both
-// sides, halving the scalar-cache footprint of M2L (forward F, backward F_L).
+// factors 2 and 1/2 are exact, so the two agree up to the compiler's choice of fused
+// operations (whole M2L outputs at orders 12-16 within 6e-17 of the largest output).  One
+// table then serves both sides, halving the scalar-cache footprint of M2L (forward F,
+// backward F_L).
 template <typename Acc, int N, int L>
 __device__ __forceinline__ void swapT_in(const Acc (&t)[N + 1], Acc xl_r, Acc xl_i, Acc (&yr)[N + 1],
                                          Acc (&yi)[N + 1])
@@ -430,6 +432,18 @@ constexpr bool lpt_transposed_l()
 {
     return sizeof(Acc) == 8 && PM >= 12;
 }
+// The same choice for the fixed-order kernel, which takes the L-side table where its
+// workgroups have 12 wavefronts (FP64 orders 13 and 14).  The transposed updates keep every
+// output of a row live, and the compiler then moves table entries through vector-register
+// lanes (about 1,900 lane moves per block at P = 16, 400 with the L-side table).  Measured
+// against the transposed read (2^20 FP64 M2L, one MI355X): P = 13 0.750 vs 0.811 ms, P = 14
+// 0.978 vs 1.020 ms with three wavefronts per SIMD; P = 15 1.259 vs 1.180 ms and P = 16 1.527
+// vs 1.466 ms with two, where the transposed read stays.
+template <typename Acc, int PM>
+constexpr bool lpt_transposed_l_fixed()
+{
+    return lpt_transposed_l<Acc, PM>() && lpt_waves<Acc, PM>() != 12;
+}
 
 // IDX: translations gather their input from the index array src and scatter to dst
 // (indexed pools); otherwise translation i of the call uses solid i of in / out.
@@ -455,8 +469,8 @@ void k_lpt(DevTables tab, TransArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
     // L-side swaps (forward for L2L, backward for M2L and L2L): from the L-side table, or
-    // from the M-side table read transposed (lpt_transposed_l)
-    constexpr bool TL = lpt_transposed_l<Acc, PM>();
+    // from the M-side table read transposed (lpt_transposed_l_fixed)
+    constexpr bool TL = lpt_transposed_l_fixed<Acc, PM>();
     constexpr bool FT = TL && OP == OP_L2L, BT = TL && OP != OP_M2M;
     const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
     const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
