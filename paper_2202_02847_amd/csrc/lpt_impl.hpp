@@ -286,10 +286,10 @@ __device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M], 
 //   Re y = D F^T D^{-1} Re x,   Im y = G^T Im x,
 // computed as updates y += x_L * (packed row L of F, G) over L = 0..N: every output sums its
 // terms in the same (ascending) order as the product with the L-side table would, and the
-// factors 2 and 1/2 are exact, so the two agree up to the compiler's choice of fused
-// operations (whole M2L outputs at orders 12-16 within 6e-17 of the largest output).  One
-// table then serves both sides, halving the scalar-cache footprint of M2L (forward F,
-// backward F_L).
+// factors 2 and 1/2 are exact, so the result is that product's (with the accumulators pinned
+// per step, see pin_all: 2^20 M2L outputs at orders 13 and 14 equal the L-side table's bit
+// for bit).  One table then serves both sides, halving the scalar-cache footprint of M2L
+// (forward F, backward F_L).
 template <typename Acc, int N, int L>
 __device__ __forceinline__ void swapT_in(const Acc (&t)[N + 1], Acc xl_r, Acc xl_i, Acc (&yr)[N + 1],
                                          Acc (&yi)[N + 1])
@@ -305,6 +305,18 @@ __device__ __forceinline__ void swapT_in(const Acc (&t)[N + 1], Acc xl_r, Acc xl
     }
 }
 
+// Makes every accumulator of a row opaque at this point.  Without it the optimiser sinks some
+// outputs' sums of the transposed update past the later steps (the sums are pure arithmetic,
+// the scalar table loads are not), so the table entries those sums need stay live across the
+// whole row and spill to vector-register lanes (at P = 16 about 1,900 lane moves per block),
+// and the sunk sums come out in another association.
+template <typename Acc, int N>
+__device__ __forceinline__ void pin_all(Acc (&y)[N + 1])
+{
+#pragma unroll
+    for (int l = 0; l <= N; ++l) asm volatile("" : "+v"(y[l]));
+}
+
 template <typename Acc, int N, int L>
 __device__ __forceinline__ void swapT_pipe(cptr<Acc> T, Acc (&cur)[N + 1], const Acc (&xr)[N + 1],
                                            const Acc (&xi)[N + 1], Acc (&yr)[N + 1], Acc (&yi)[N + 1])
@@ -313,6 +325,8 @@ __device__ __forceinline__ void swapT_pipe(cptr<Acc> T, Acc (&cur)[N + 1], const
         Acc nxt[N + 1];
         swap_fetch<Acc, N, L + 1>(T, nxt);
         swapT_in<Acc, N, L>(cur, L == 0 ? xr[0] * (Acc)0.5 : xr[L], xi[L], yr, yi);
+        pin_all<Acc, N>(yr);
+        pin_all<Acc, N>(yi);
         __builtin_amdgcn_sched_barrier(0);
         swapT_pipe<Acc, N, L + 1>(T, nxt, xr, xi, yr, yi);
     }
@@ -426,23 +440,12 @@ constexpr bool lpt_prefetch_ok()
 // Whether the L-side swaps read the M-side table transposed (swap_row_x) instead of the
 // L-side table.  Measured on MI355X (FP64 M2L, 2^20 translations): at order 10 the L-side
 // table is faster (0.385 vs 0.468 ms); from order 12 one table in the scalar cache wins
-// (P = 12: 0.675 vs 0.690 ms, P = 16: 1.41 vs 1.48 ms).
+// (P = 12: 0.675 vs 0.690 ms, P = 16: 1.41 vs 1.48 ms; with the accumulators pinned, 1.391 ms
+// against 1.527 for the L-side table and 1.445 for the unpinned transposed read).
 template <typename Acc, int PM>
 constexpr bool lpt_transposed_l()
 {
     return sizeof(Acc) == 8 && PM >= 12;
-}
-// The same choice for the fixed-order kernel, which takes the L-side table where its
-// workgroups have 12 wavefronts (FP64 orders 13 and 14).  The transposed updates keep every
-// output of a row live, and the compiler then moves table entries through vector-register
-// lanes (about 1,900 lane moves per block at P = 16, 400 with the L-side table).  Measured
-// against the transposed read (2^20 FP64 M2L, one MI355X): P = 13 0.750 vs 0.811 ms, P = 14
-// 0.978 vs 1.020 ms with three wavefronts per SIMD; P = 15 1.259 vs 1.180 ms and P = 16 1.527
-// vs 1.466 ms with two, where the transposed read stays.
-template <typename Acc, int PM>
-constexpr bool lpt_transposed_l_fixed()
-{
-    return lpt_transposed_l<Acc, PM>() && lpt_waves<Acc, PM>() != 12;
 }
 
 // IDX: translations gather their input from the index array src and scatter to dst
@@ -469,8 +472,8 @@ void k_lpt(DevTables tab, TransArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     using T = Tab<Real, Acc>;
     // L-side swaps (forward for L2L, backward for M2L and L2L): from the L-side table, or
-    // from the M-side table read transposed (lpt_transposed_l_fixed)
-    constexpr bool TL = lpt_transposed_l_fixed<Acc, PM>();
+    // from the M-side table read transposed (lpt_transposed_l)
+    constexpr bool TL = lpt_transposed_l<Acc, PM>();
     constexpr bool FT = TL && OP == OP_L2L, BT = TL && OP != OP_M2M;
     const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
     const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
