@@ -252,8 +252,8 @@ __device__ __forceinline__ void swap_row(cptr<Acc> T, const Acc (&xr)[N + 1], co
 // stay resident instead of one block of lines per column.  The normalised tables (FP32) are
 // read per column.  Entries outside the triangle of M2M / L2L are returned as 0 (unused).
 // single (M2L only): the single-height kernel (eq. m2lkernels, left) keeps the terms with
-// o + k <= PIN - 1; the others are returned as 0.  The coefficients are wave-uniform, so
-// the selection is a scalar operation and the double-height code runs unchanged.
+// o + k <= PIN - 1; the others are returned as 0.  The fixed-order kernel passes it as a
+// compile-time constant (a kernel form of its own), so neither form carries the selection.
 template <typename Real, typename Acc, int OP, int PIN, int M>
 __device__ __forceinline__ void z_fetch(cptr<Acc> Z0, int o, Acc (&c)[PIN - M], bool single = false)
 {
@@ -450,7 +450,10 @@ constexpr bool lpt_transposed_l()
 
 // IDX: translations gather their input from the index array src and scatter to dst
 // (indexed pools); otherwise translation i of the call uses solid i of in / out.
-template <typename Real, typename Acc, int OP, int PIN, int POUT, bool IDX>
+// SGL (M2L only): the single-height z-step, a compile-time choice so that the double-height
+// kernel carries no per-coefficient selection (2^20 FP64 M2L, one MI355X: a run-time flag
+// cost 3% at P = 13, 15 and 16 and 7% at P = 14, in scalar selects on the z-step's path).
+template <typename Real, typename Acc, int OP, int PIN, int POUT, bool IDX, bool SGL>
 __global__ __launch_bounds__((64 * lpt_waves<Acc, (PIN > POUT ? PIN : POUT)>()),
                              (lpt_min_waves_nw<Acc, (PIN > POUT ? PIN : POUT)>()))
 void k_lpt(DevTables tab, TransArgs a)
@@ -478,7 +481,8 @@ void k_lpt(DevTables tab, TransArgs a)
     const cptr<Acc> Pfw0 = as_const(T::packed(tab, (OP == OP_L2L && !TL) ? 1 : 0));
     const cptr<Acc> Pbw0 = as_const(T::packed(tab, (OP != OP_M2M && !TL) ? 1 : 0));
     const cptr<Acc> Z0 = as_const(T::z(tab, OP));
-    const bool single = OP == OP_M2L && (a.flags & kSingleHeightFlag) != 0;
+    static_assert(!SGL || OP == OP_M2L, "single height is an M2L form");
+    constexpr bool single = SGL;
     const Real *__restrict__ rr = reinterpret_cast<const Real *>(a.r);
     const Real *__restrict__ gin = reinterpret_cast<const Real *>(a.in);
     Real *__restrict__ gout = reinterpret_cast<Real *>(a.out);
@@ -805,15 +809,24 @@ void k_lpt(DevTables tab, TransArgs a)
 // Workgroups resident at once on the current device for kernel fn (CU count x occupancy).
 int resident_workgroups(const void *fn);
 
-template <typename Real, typename Acc, int OP, int PV, bool IDX>
-hipError_t launch_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
+template <typename Real, typename Acc, int OP, int PV, bool IDX, bool SGL>
+hipError_t launch_one_form(const DevTables &tab, const TransArgs &a, hipStream_t s)
 {
-    const void *fn = reinterpret_cast<const void *>(&k_lpt<Real, Acc, OP, PV, PV, IDX>);
+    const void *fn = reinterpret_cast<const void *>(&k_lpt<Real, Acc, OP, PV, PV, IDX, SGL>);
     const int64_t nblk = (a.count + 63) / 64;
     const int64_t res = resident_workgroups(fn);
     const dim3 grid((unsigned)(nblk < res ? nblk : res)), block(64 * lpt_waves<Acc, PV>());
-    hipLaunchKernelGGL((k_lpt<Real, Acc, OP, PV, PV, IDX>), grid, block, 0, s, tab, a);
+    hipLaunchKernelGGL((k_lpt<Real, Acc, OP, PV, PV, IDX, SGL>), grid, block, 0, s, tab, a);
     return hipGetLastError();
+}
+
+template <typename Real, typename Acc, int OP, int PV, bool IDX>
+hipError_t launch_one(const DevTables &tab, const TransArgs &a, hipStream_t s)
+{
+    if constexpr (OP == OP_M2L) {
+        if ((a.flags & kSingleHeightFlag) != 0) return launch_one_form<Real, Acc, OP, PV, IDX, true>(tab, a, s);
+    }
+    return launch_one_form<Real, Acc, OP, PV, IDX, false>(tab, a, s);
 }
 
 // Launcher for one (dtype, op); instantiated in the k_lpt_<dtype>_<op>.hip units.

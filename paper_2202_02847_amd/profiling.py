@@ -7,7 +7,7 @@ each is scaled by the factor that makes the same counter read the known size of 
 plain 1 GiB copy that the counter program runs first.
 
     python -m paper_2202_02847_amd.profiling traffic --fetch F.csv --write W.csv \\
-        --kernel "k_lpt<double, double, 1, 10, 10, false>" --bytes-per-launch B --out X.json
+        --kernel "k_lpt<double, double, 1, 10, 10, false, false>" --bytes-per-launch B --out X.json
 
 writes the per-launch fetch/write bytes, the scale factors and a hash of the kernel
 sources; bench.py reports the traffic only while that hash matches the current sources.
