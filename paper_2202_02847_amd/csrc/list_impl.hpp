@@ -178,15 +178,16 @@ void k_list_lpt(DevTables tab, ListArgs la)
                                 Acc nz[PB - m];
                                 if (o + 1 < PB) z_fetch<Real, Acc, OP, PB, m>(Z, o + 1, nz);
                                 if (o < p_out) {
+                                    // rows k >= p_in are zero in ir / ii, so their terms add
+                                    // exact zeros: no per-term test (the compiler turned a test
+                                    // on the task's p_in here into four selects per term)
                                     Acc orr = 0, oi = 0;
 #pragma unroll
                                     for (int k = m; k < PB; ++k) {
                                         if (OP == OP_M2M && k > o) continue;
                                         if (OP == OP_L2L && k < o) continue;
-                                        if (k < p_in) {
-                                            orr += cz[k - m] * ir[k];
-                                            oi += cz[k - m] * ii[k];
-                                        }
+                                        orr += cz[k - m] * ir[k];
+                                        oi += cz[k - m] * ii[k];
                                     }
                                     *reinterpret_cast<P2 *>(&Xt[solid_pos(o, m)]) = P2{orr, oi};
                                 }
