@@ -441,11 +441,14 @@ constexpr bool lpt_prefetch_ok()
 // L-side table.  Measured on MI355X (FP64 M2L, 2^20 translations): at order 10 the L-side
 // table is faster (0.385 vs 0.468 ms); from order 12 one table in the scalar cache wins
 // (P = 12: 0.675 vs 0.690 ms, P = 16: 1.41 vs 1.48 ms; with the accumulators pinned, 1.391 ms
-// against 1.527 for the L-side table and 1.445 for the unpinned transposed read).
+// against 1.527 for the L-side table and 1.445 for the unpinned transposed read).  The FP32
+// tables (normalised basis) satisfy the same identity, and with the accumulators pinned the FP32
+// kernel gains as well (P = 14: 0.512 vs 0.633 ms, P = 16: 0.915 vs 1.043 ms, P = 12 equal;
+// outputs bit-identical to the L-side table's).
 template <typename Acc, int PM>
 constexpr bool lpt_transposed_l()
 {
-    return sizeof(Acc) == 8 && PM >= 12;
+    return PM >= 12;
 }
 
 // IDX: translations gather their input from the index array src and scatter to dst
