@@ -514,13 +514,18 @@ void k_lpt(DevTables tab, TransArgs a)
     const int64_t *__restrict__ gsrc = a.src;
     const int64_t *__restrict__ gdst = a.dst;
     // issue the loads of pairs c0 + tid + NT i (i < CH) of the block at bb (ntb translations)
+    // IDX: each lane loads the source index of translation `lane` of the block once, and the
+    // loads of a pair take their translation's index from that lane by a cross-lane read (one
+    // global load per lane instead of one per pair; with the destination indices read the same
+    // way, 2^20 FP64 M2L with sorted indices at P = 10: 0.439 ms, from 0.457)
     auto load_batch = [&](int64_t bb, int ntb, int c0) {
         int64_t row[IDX ? CH : 1];
         if constexpr (IDX) {
+            const long mine = gsrc[bb + (lane < ntb ? lane : ntb - 1)];
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const int t = (c0 + tid + NT * i) / (SIN / 2);
-                row[i] = gsrc[bb + (t < ntb ? t : ntb - 1)];
+                row[i] = __shfl(mine, t < ntb ? t : ntb - 1, 64);
             }
         }
         // block base (wave-uniform, 64-bit) + 32-bit per-lane offsets (ld_in < 2^24)
@@ -564,6 +569,10 @@ void k_lpt(DevTables tab, TransArgs a)
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const int64_t base = blk * 64;
         const int nt = block_count(blk);
+        // IDX: destination index of translation `lane` of this block, loaded now so that the
+        // store phase reads it from this lane without waiting on memory
+        long dmine = 0;
+        if constexpr (IDX) dmine = gdst[base + (lane < nt ? lane : nt - 1)];
         const cptr<Acc> Pfw = launder(Pfw0), Pbw = launder(Pbw0), Z = launder(Z0);
         if constexpr (PREFETCH) {
             store_batch_lds(0);
@@ -740,10 +749,11 @@ void k_lpt(DevTables tab, TransArgs a)
             Real *__restrict__ bout = gout + base * a.ld_out;  // block base + 32-bit offsets
             const int ldo = (int)a.ld_out;
             if constexpr (IDX) {
+                // destination indices from the lanes that loaded them at the block's start
 #pragma unroll
                 for (int i = 0; i < SIT; ++i) {
                     const int t = (tid + NT * i) / (SOUT / 2);
-                    drow[i] = gdst[base + (t < nt ? t : nt - 1)];
+                    drow[i] = __shfl(dmine, t < nt ? t : nt - 1, 64);
                 }
             }
             if (nt == 64) {
